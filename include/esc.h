@@ -1,0 +1,285 @@
+/*
+ * esc.h -- C ABI of the MI355X (gfx950) exact selectivity computation library.
+ *
+ * Exact selectivity computation (ESC; Section 2, "Exact Selectivity
+ * Computation") replaces a cardinality estimate by the exact answer of the
+ * sub-query  SELECT COUNT(*) FROM R WHERE P  run at optimisation time, and
+ * optionally keeps the qualifying rows, restricted to the pushed-down
+ * projection, as a temporary table in GPU memory for reuse by the plan
+ * (Section 2 and Section 2.1, "Selection Materialization").
+ *
+ * Conventions for every call:
+ *  - every function returns an esc_status; out-parameters are written only
+ *    on ESC_OK (the one exception, ESC_ERR_CAPACITY, is documented at
+ *    esc_materialize); a message for the last failure of the calling thread
+ *    is available from esc_last_error();
+ *  - no C++ exception crosses this boundary and nothing aborts;
+ *  - "device pointer" means memory of the GPU the context was created on
+ *    (hipMalloc'd or a torch CUDA tensor); the caller owns every device
+ *    buffer passed in (columns, outputs, workspaces) and keeps it alive for
+ *    the duration of the call (of the batch, for batched handles); the
+ *    library never frees them;
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *  - handles are created and destroyed by the library; a handle may be used
+ *    from one thread at a time.
+ */
+#ifndef ESC_H
+#define ESC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ESC_ABI_VERSION 1
+
+/* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
+typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
+
+typedef enum {
+    ESC_OK = 0,
+    ESC_ERR_INVALID = -1,      /* malformed tree, bad index, null handle, bad size */
+    ESC_ERR_TYPE = -2,         /* constant dtype differs from its column, float in a udf */
+    ESC_ERR_CAPACITY = -3,     /* materialized rows exceed the output capacity */
+    ESC_ERR_ALIGN = -4,        /* a device column is not 16-byte aligned */
+    ESC_ERR_HIP = -5,          /* a HIP runtime call failed (message has the HIP error) */
+    ESC_ERR_OOM = -6,          /* host or device allocation failed, or workspace too small */
+    ESC_ERR_UNSUPPORTED = -7,  /* valid but beyond the compiled limits (see ESC_MAX_*) */
+    ESC_ERR_TIMEOUT = -8       /* a kernel's bounded wait expired; results are undefined */
+} esc_status;
+
+/* Limits of one compiled predicate. */
+#define ESC_MAX_COLUMNS_PER_PRED 8   /* distinct columns referenced */
+#define ESC_MAX_INSNS 64             /* device instructions after normalisation */
+#define ESC_MAX_CONSTS 256           /* IN-list constants after de-duplication */
+#define ESC_MAX_IN 64                /* constants in one IN-list */
+#define ESC_MAX_CLAUSES 32           /* conjuncts after conversion to AND-of-ORs */
+#define ESC_MAX_PROJ 8               /* projected columns of one materialization */
+
+/* ------------------------------------------------------------------ predicates
+ *
+ * The predicate language of the paper's example selection (Section 1):
+ * equality, ranges, BETWEEN, OR-ed alternatives and a deterministic integer
+ * user-defined function compared with a constant, combined with AND / OR;
+ * plus IN-lists.  A predicate is an array of esc_node in pre-order: an
+ * AND/OR node is followed by its `nchild` direct children (each with its own
+ * subtree), a leaf has no children.
+ *
+ * Semantics:
+ *  EQ  v == k      LT  v < k      GT  v > k      BETWEEN  k0 <= v && v <= k1
+ *  IN  v equals some listed constant (duplicates allowed, list non-empty)
+ *  int32/date32 compare as int32; float32 uses IEEE ordered comparisons
+ *  (NaN matches nothing, -0.0 == +0.0, denormals compare exactly).
+ *  UDF: an int32 expression over int32/date32 columns and constants,
+ *  evaluated with two's-complement wrap-around, then compared like a leaf
+ *  (op `cmp`, int32 constants).  No NULLs: every row participates.
+ */
+typedef enum {
+    ESC_AND = 0, ESC_OR = 1, ESC_EQ = 2, ESC_LT = 3, ESC_GT = 4,
+    ESC_BETWEEN = 5, ESC_IN = 6, ESC_UDF = 7
+} esc_op;
+
+typedef union { int32_t i; float f; uint32_t bits; } esc_value;
+
+/* A typed constant: `dtype` must equal the dtype of the column it is
+ * compared with (ESC_INT32 for udf comparisons and udf operands). */
+typedef struct { int32_t dtype; esc_value v; } esc_const;
+
+typedef struct {
+    int32_t op;      /* esc_op */
+    int32_t col;     /* EQ..IN: 0-based column index; otherwise ignored */
+    int32_t nchild;  /* AND/OR: number of direct children (>= 1); otherwise 0 */
+    int32_t cmp;     /* UDF: ESC_EQ..ESC_IN, the comparison of the udf value */
+    int32_t k0, k1;  /* constants (indices into `consts`): EQ/LT/GT consts[k0];
+                        BETWEEN lo = consts[k0], hi = consts[k1];
+                        IN consts[k0 .. k0 + k1) (k1 = list length);
+                        UDF: the same, according to `cmp` */
+    int32_t u0, u1;  /* UDF: program udf[u0 .. u0 + u1) */
+} esc_node;
+
+/* udf program: an accumulator machine.  The first instruction is ESC_U_LOAD;
+ * each later one sets acc = acc <op> operand.  The operand is a column
+ * (src = ESC_U_COL, arg = column index, int32/date32 only) or an int32
+ * constant (src = ESC_U_CONST, arg = value).  MOD is the truncated
+ * remainder (sign of the dividend) by a positive constant; SHL / SHR shift
+ * by a constant in [0, 31], SHR arithmetic.  Left-deep expressions such as
+ * (31*B + D) mod 97 map onto it directly. */
+typedef enum {
+    ESC_U_LOAD = 0, ESC_U_ADD = 1, ESC_U_SUB = 2, ESC_U_MUL = 3, ESC_U_MOD = 4,
+    ESC_U_AND = 5, ESC_U_OR = 6, ESC_U_XOR = 7, ESC_U_SHL = 8, ESC_U_SHR = 9
+} esc_udf_op;
+typedef enum { ESC_U_COL = 0, ESC_U_CONST = 1 } esc_udf_src;
+typedef struct { int32_t op, src, arg; } esc_udf_insn;
+
+typedef struct esc_ctx esc_ctx;
+typedef struct esc_table esc_table;
+typedef struct esc_pred esc_pred;
+typedef struct esc_batch esc_batch;
+typedef struct esc_mlp esc_mlp;
+
+/* Message of the calling thread's last failure ("" if none).  The pointer
+ * stays valid until the thread's next failing call. */
+const char *esc_last_error(void);
+int esc_abi_version(void);
+
+/* ------------------------------------------------------------------ context */
+
+/* Binds HIP device `device`, reads its properties and allocates a small
+ * pinned host buffer for results.  ESC_ERR_HIP when the device is absent. */
+int esc_ctx_create(int device, esc_ctx **out);
+int esc_ctx_destroy(esc_ctx *ctx);
+/* Number of compute units of the context's device. */
+int esc_ctx_num_cus(const esc_ctx *ctx, int *out);
+
+/* ------------------------------------------------------------------ tables
+ *
+ * A column-wise in-memory table (Section 2: column-wise in-memory databases
+ * read only the columns a query needs).  `dev_cols[c]` is a device pointer
+ * to nrows 4-byte values of dtype dtypes[c], 16-byte aligned (else
+ * ESC_ERR_ALIGN).  dev_cols == NULL creates a schema-only table: it can
+ * compile and featurize predicates but not be scanned.  The table borrows
+ * the column pointers.  0 <= nrows <= 2^31 - 1 (row ids are int32),
+ * 1 <= ncols <= 64. */
+int esc_table_create(int64_t nrows, int ncols, const int32_t *dtypes,
+                     const void *const *dev_cols, esc_table **out);
+int esc_table_destroy(esc_table *t);
+
+/* ------------------------------------------------------------------ compile
+ *
+ * Validates and type-checks the tree against `schema`, converts it to an
+ * AND of OR-clauses (distributing OR over AND; exact, since the language
+ * has no negation), folds leaves that are constant (e.g. LT INT32_MIN, a
+ * NaN bound, an empty BETWEEN), normalises each leaf to a range, bitmap or
+ * set test and emits a wave-uniform device program.  Host only: works
+ * without a GPU.  Errors: ESC_ERR_INVALID (structure, indices, empty IN,
+ * udf modulus <= 0, shift outside [0,31], udf not starting with LOAD),
+ * ESC_ERR_TYPE (constant dtype mismatch, float32 column in a udf),
+ * ESC_ERR_UNSUPPORTED (more than the ESC_MAX_* limits). */
+int esc_compile_predicate(const esc_table *schema, const esc_node *nodes, int nnodes,
+                          const esc_const *consts, int nconsts,
+                          const esc_udf_insn *udf, int nudf, esc_pred **out);
+int esc_pred_destroy(esc_pred *p);
+
+typedef struct {
+    int32_t nclauses;     /* conjuncts after normalisation */
+    int32_t ninsns;       /* device instructions */
+    int32_t ncols;        /* distinct columns read by a scan */
+    int32_t constant;     /* 0: data-dependent; 1: always true; -1: always false */
+    uint64_t col_mask;    /* bit c set when column c is read (c < 64) */
+} esc_pred_info;
+int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);
+
+/* ------------------------------------------------------------------ scans
+ *
+ * Workspace: device memory of at least esc_workspace_size() bytes, 256-byte
+ * aligned, zero-filled before its first use (esc_workspace_init does that);
+ * every successful call leaves it ready for the next call.  Calls that may
+ * overlap in time (different streams) need distinct workspaces. */
+int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes);
+int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* Exact COUNT(*) of the selection (Section 2: the selectivity sub-query
+ * with a temporary COUNT aggregate).  Blocks until the count is on the
+ * host. */
+int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+              void *dev_ws, size_t ws_bytes, void *stream, uint64_t *out_count);
+
+/* Same scan, asynchronous: the count is written to device memory
+ * `dev_count` (8 bytes) in stream order; nothing waits. */
+int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+                    void *dev_ws, size_t ws_bytes, void *stream, uint64_t *dev_count);
+
+/* The selection together with its pushed-down projection (Section 2) kept
+ * as a temporary table (Section 2.1): dev_rowids[r] is the r-th qualifying
+ * row in ascending row order, dev_proj_out[j][r] the value of column
+ * proj_cols[j] at that row, bit for bit.  Outputs are caller-owned device
+ * buffers of `capacity` elements (rowids int32, projections 4 bytes).
+ * Blocks until the count is on the host.  When the count exceeds
+ * `capacity`, the first `capacity` rows are written, *out_count receives the
+ * full count and ESC_ERR_CAPACITY is returned.  0 <= nproj <= ESC_MAX_PROJ;
+ * dev_rowids may be NULL when only projections are wanted. */
+int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+                    const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
+                    void *const *dev_proj_out, uint64_t capacity,
+                    void *dev_ws, size_t ws_bytes, void *stream, uint64_t *out_count);
+
+/* ------------------------------------------------------------------ batched
+ *
+ * "The same procedure is applied to each table having selection predicates"
+ * (Section 2): many selectivity sub-queries at once.  One persistent kernel
+ * reads each table's columns once per predicate group and counts every
+ * predicate of the group; the whole launch is captured in a hipGraph.
+ * The batch allocates its own device memory (work list, programs, counts)
+ * and keeps the tables' column pointers. */
+typedef struct {
+    int32_t autotune;        /* 1: time candidate configurations at create */
+    int32_t block;           /* threads per block (256 or 512); 0 = default */
+    int32_t rows_per_thread; /* 8 or 16; 0 = default */
+    int32_t group;           /* predicates evaluated per pass over a chunk; 0 = all of the table's */
+    int32_t chunk_rows;      /* rows per work item; 0 = default */
+    int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
+} esc_batch_opts;
+
+int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,
+                     const esc_pred *const *preds, const int32_t *pred_table, int npreds,
+                     const esc_batch_opts *opts, void *stream, esc_batch **out);
+/* New predicates for the same tables (pred_table unchanged); recompiles the
+ * work list if the predicates' column sets changed. */
+int esc_batch_update(esc_batch *b, const esc_pred *const *preds, int npreds, void *stream);
+/* Launches the graph and waits; out_counts[i] = exact count of preds[i]. */
+int esc_batch_count(esc_batch *b, void *stream, uint64_t *out_counts);
+/* The configuration in use (after tuning). */
+int esc_batch_get_opts(const esc_batch *b, esc_batch_opts *out);
+int esc_batch_destroy(esc_batch *b);
+
+/* ------------------------------------------------------------------ learned gate
+ *
+ * Featurization of predicates into 64 float32 values:
+ * per column c < 6: [present, lo, hi, is_eq, is_lt, is_gt, is_between, is_in,
+ * in_size/16, in_or] then [n_conj/6, n_or/6, has_udf, n_leaves/16]; bounds
+ * normalised with the catalog minimum / maximum of each column (col_min /
+ * col_max, in the column's dtype).  Host only. */
+int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
+                  const esc_pred *const *preds, int npreds, float *host_out);
+
+/* MLP 64 -> 256 -> 256 -> 256 -> 1 (ReLU) predicting ln(selectivity).
+ * bfloat16 MFMA operands, float32 accumulation, float32 master weights and
+ * Adam state on the device.  Parameters are exchanged as one float32 array
+ * in the order W1[64][256], b1[256], W2[256][256], b2[256], W3[256][256],
+ * b3[256], W4[256], b4[1] (ESC_MLP_NPARAMS values, weights [fan_in][fan_out]). */
+#define ESC_MLP_NPARAMS 148481
+int esc_mlp_create(esc_ctx *ctx, esc_mlp **out);
+int esc_mlp_destroy(esc_mlp *m);
+int esc_mlp_set_params(esc_mlp *m, const float *host_params);   /* also resets Adam */
+int esc_mlp_get_params(esc_mlp *m, float *host_params);
+/* yhat[i] for n rows of dev_x (n x 64 float32, device) into dev_yhat. */
+int esc_mlp_predict(esc_mlp *m, const float *dev_x, int64_t n, float *dev_yhat, void *stream);
+/* Gradient of mean((yhat - y)^2) over the n rows (n <= 4096), written as a
+ * flat float32 array in the parameter order into dev_grads. */
+int esc_mlp_gradients(esc_mlp *m, const float *dev_x, const float *dev_y, int64_t n,
+                      float *dev_grads, void *stream);
+/* Minibatch Adam: `steps` steps; step s uses rows dev_order[s*batch ..
+ * (s+1)*batch) of (dev_x, dev_y); batch in [1, 4096].  host_loss, if not
+ * NULL, receives the mean loss of each step (steps floats).  Adam betas
+ * 0.9 / 0.999, eps 1e-8. */
+int esc_mlp_train(esc_mlp *m, const float *dev_x, const float *dev_y, const int32_t *dev_order,
+                  int64_t steps, int batch, float lr, void *stream, float *host_loss);
+
+/* Gate (Section 2.1 and 2.2 read as plan-flip tests): route[i] = 1 when the
+ * predicted selectivity s = clamp(exp(yhat[i]), 1/n, 1) of a table with
+ * n = nrows[i] >= min_rows lies in [tau/beta, tau*beta], i.e. the push-down
+ * decision "selectivity below tau" could flip within the estimator's error
+ * factor beta (> 1). */
+int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau, double beta,
+                      int64_t min_rows, uint8_t *route);
+/* route = 1 when the predicted filtered sizes of two build relations are
+ * within a factor beta^2 of each other, so their join order could flip. */
+int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta,
+                       uint8_t *route);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESC_H */

@@ -1,0 +1,231 @@
+// esc_api.hip -- context, workspace and the host side of esc_count /
+// esc_materialize: validation, choice of the kernel variant, launch and the
+// 8-byte (or 64-byte) read-back of the result.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+
+#include "esc_host.h"
+#include "esc_kernels.h"
+#include "esc_runtime.h"
+
+using esc::fail;
+
+namespace esc {
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(ESC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static std::mutex g_occ_mu;
+static std::map<const void *, int> g_occ;
+
+int occupancy(const void *fn, int block, int dyn_lds)
+{
+    std::lock_guard<std::mutex> g(g_occ_mu);
+    auto it = g_occ.find(fn);
+    if (it != g_occ.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, dyn_lds) != hipSuccess || nb <= 0) nb = 1;
+    g_occ[fn] = nb;
+    return nb;
+}
+
+int check_scan_args(const esc_ctx *ctx, const esc_table *t, const esc_pred *p, const void *ws, size_t ws_bytes,
+                    size_t need)
+{
+    if (!ctx || !t || !p) return fail(ESC_ERR_INVALID, "null handle");
+    if (!t->has_data()) return fail(ESC_ERR_INVALID, "table is schema-only (no device columns)");
+    if (p->schema_dtypes != t->dtypes)
+        return fail(ESC_ERR_INVALID, "predicate was compiled for a different schema");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(ESC_ERR_ALIGN, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < need) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return ESC_OK;
+}
+
+ColPtrs slot_ptrs(const esc_table *t, const Program &P)
+{
+    ColPtrs cp{};
+    for (int s = 0; s < P.nslots; s++) cp.p[s] = (const uint32_t *)t->cols[P.slot_col[s]];
+    return cp;
+}
+
+__global__ void store_u64_kernel(unsigned long long *dst, unsigned long long v) { *dst = v; }
+
+}  // namespace esc
+
+using namespace esc;
+
+extern "C" {
+
+int esc_ctx_create(int device, esc_ctx **out)
+{
+    if (!out) return fail(ESC_ERR_INVALID, "null output handle");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(ESC_ERR_HIP, "no HIP device available");
+    if (device < 0 || device >= n) return fail(ESC_ERR_INVALID, "device %d outside [0, %d)", device, n);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    esc_ctx *c = new (std::nothrow) esc_ctx;
+    if (!c) return fail(ESC_ERR_OOM, "out of host memory");
+    c->device = device;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) { delete c; return hip_fail(e, "hipGetDeviceProperties"); }
+    c->num_cus = prop.multiProcessorCount;
+    if ((e = hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipHostMalloc");
+    }
+    const char *r = getenv("ESC_COUNT_RPT");
+    if (r && (atoi(r) == 4 || atoi(r) == 8)) c->rpt_count = atoi(r);
+    r = getenv("ESC_MAT_RPT");
+    if (r && (atoi(r) == 4 || atoi(r) == 8)) c->rpt_mat = atoi(r);
+    *out = c;
+    return ESC_OK;
+}
+
+int esc_ctx_destroy(esc_ctx *ctx)
+{
+    if (!ctx) return ESC_OK;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return ESC_OK;
+}
+
+int esc_ctx_num_cus(const esc_ctx *ctx, int *out)
+{
+    if (!ctx || !out) return fail(ESC_ERR_INVALID, "null argument");
+    *out = ctx->num_cus;
+    return ESC_OK;
+}
+
+int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
+{
+    if (!t || !bytes) return fail(ESC_ERR_INVALID, "null argument");
+    size_t need = sizeof(WsHeader);
+    if (materialize) {
+        // tiles of the smallest variant (RPT = 4)
+        const int64_t tile = (int64_t)kScanBlock * 4;
+        need += (size_t)((t->nrows + tile - 1) / tile) * 8;
+    }
+    *bytes = (need + 255) & ~(size_t)255;
+    return ESC_OK;
+}
+
+int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx || !dev_ws || ws_bytes < sizeof(WsHeader)) return fail(ESC_ERR_INVALID, "bad workspace");
+    (void)hipSetDevice(ctx->device);
+    launch_zero((unsigned long long *)dev_ws, (int64_t)(ws_bytes / 8), (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ESC_OK : hip_fail(e, "zero kernel launch");
+}
+
+static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
+                        hipStream_t s, unsigned long long *dev_out)
+{
+    int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
+    if (rc) return rc;
+    (void)hipSetDevice(ctx->device);
+    const Program &P = p->prog;
+    if ((P.flags & (P_ALWAYS_FALSE | P_ALWAYS_TRUE)) || t->nrows == 0) {
+        const unsigned long long v = (P.flags & P_ALWAYS_TRUE) ? (unsigned long long)t->nrows : 0ull;
+        hipLaunchKernelGGL(store_u64_kernel, dim3(1), dim3(1), 0, s, dev_out, v);
+    } else {
+        const int rpt = ctx->rpt_count;
+        CountFn fn = count_fn(P.nslots, rpt);
+        const int64_t tile = (int64_t)kScanBlock * rpt;
+        const int64_t ntiles = (t->nrows + tile - 1) / tile;
+        int64_t grid = (int64_t)ctx->num_cus * occupancy((const void *)fn, kScanBlock, 0);
+        if (grid > ntiles) grid = ntiles;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P), t->nrows,
+                           (WsHeader *)dev_ws, dev_out);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ESC_OK : hip_fail(e, "count kernel launch");
+}
+
+int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes, void *stream,
+              uint64_t *out_count)
+{
+    if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
+    hipStream_t s = (hipStream_t)stream;
+    WsHeader *h = (WsHeader *)dev_ws;
+    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, h ? &h->result : nullptr);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(ctx->pinned, &h->result, 8, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    *out_count = ctx->pinned[0];
+    return ESC_OK;
+}
+
+int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
+                    void *stream, uint64_t *dev_count)
+{
+    if (!dev_count) return fail(ESC_ERR_INVALID, "null dev_count");
+    return count_launch(ctx, t, p, dev_ws, ws_bytes, (hipStream_t)stream, (unsigned long long *)dev_count);
+}
+
+int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols, int nproj,
+                    int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity, void *dev_ws,
+                    size_t ws_bytes, void *stream, uint64_t *out_count)
+{
+    if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
+    size_t need = 0;
+    int rc = t ? esc_workspace_size(t, 1, &need) : fail(ESC_ERR_INVALID, "null table");
+    if (rc) return rc;
+    if ((rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, need))) return rc;
+    if (nproj < 0 || nproj > ESC_MAX_PROJ) return fail(ESC_ERR_INVALID, "nproj %d outside [0, %d]", nproj, ESC_MAX_PROJ);
+    if (nproj > 0 && !proj_cols) return fail(ESC_ERR_INVALID, "null proj_cols");
+    if (capacity > 0 && nproj > 0 && !dev_proj_out) return fail(ESC_ERR_INVALID, "null projection outputs");
+    const Program &P = p->prog;
+    ProjArgs pa{};
+    pa.nproj = nproj;
+    const int ncols = (int)t->dtypes.size();
+    for (int q = 0; q < nproj; q++) {
+        const int c = proj_cols[q];
+        if (c < 0 || c >= ncols) return fail(ESC_ERR_INVALID, "projected column %d out of range", c);
+        if (capacity > 0 && !dev_proj_out[q]) return fail(ESC_ERR_INVALID, "projection output %d is null", q);
+        pa.slot[q] = -1;
+        for (int s = 0; s < P.nslots; s++)
+            if (P.slot_col[s] == c) pa.slot[q] = s;
+        pa.src[q] = (const uint32_t *)t->cols[c];
+        pa.dst[q] = capacity > 0 ? (uint32_t *)dev_proj_out[q] : nullptr;
+    }
+    if ((P.flags & P_ALWAYS_FALSE) || t->nrows == 0) {
+        *out_count = 0;
+        return ESC_OK;
+    }
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int rpt = ctx->rpt_mat;
+    const int64_t tile = (int64_t)kScanBlock * rpt;
+    const int ntiles = (int)((t->nrows + tile - 1) / tile);
+    WsHeader *h = (WsHeader *)dev_ws;
+    unsigned long long *status = (unsigned long long *)(h + 1);
+    launch_zero((unsigned long long *)dev_ws, (int64_t)(sizeof(WsHeader) / 8) + ntiles, s);
+    MatFn fn = mat_fn(P.nslots, rpt);
+    int64_t grid = (int64_t)ctx->num_cus * occupancy((const void *)fn, kScanBlock, 0);
+    if (grid > ntiles) grid = ntiles;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P), t->nrows, ntiles, pa,
+                       capacity > 0 ? dev_rowids : nullptr, (unsigned long long)capacity, h, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "materialize kernel launch");
+    if ((e = hipMemcpyAsync(ctx->pinned, h, sizeof(WsHeader), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const WsHeader *hh = (const WsHeader *)ctx->pinned;
+    if (hh->error) return fail(ESC_ERR_TIMEOUT, "look-back wait expired; results undefined");
+    *out_count = hh->result;
+    if (hh->result > capacity) return fail(ESC_ERR_CAPACITY, "%llu rows qualify, capacity %llu", hh->result,
+                                           (unsigned long long)capacity);
+    return ESC_OK;
+}
+
+}  // extern "C"

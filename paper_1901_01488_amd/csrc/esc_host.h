@@ -1,0 +1,40 @@
+// esc_host.h -- host-side objects behind the opaque handles of esc.h.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "esc.h"
+#include "esc_program.h"
+
+struct esc_table {
+    int64_t nrows = 0;
+    std::vector<int32_t> dtypes;
+    std::vector<const void *> cols;   // empty for a schema-only table
+    bool has_data() const { return !cols.empty(); }
+};
+
+struct esc_pred {
+    esc::Program prog{};
+    int ncols_schema = 0;
+    std::vector<int32_t> schema_dtypes;
+    // the source tree, kept for featurization
+    std::vector<esc_node> nodes;
+    std::vector<esc_const> consts;
+    std::vector<esc_udf_insn> udf;
+    uint64_t col_mask = 0;
+};
+
+namespace esc {
+
+// thread-local error message; returns `status` so callers can `return fail(...)`
+int fail(int status, const char *fmt, ...);
+void clear_error();
+
+// host compiler (no HIP): fills p->prog from the tree
+int compile(const esc_table *schema, const esc_node *nodes, int nnodes,
+            const esc_const *consts, int nconsts, const esc_udf_insn *udf, int nudf,
+            esc_pred *p);
+
+}  // namespace esc

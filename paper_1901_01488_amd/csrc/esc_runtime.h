@@ -1,0 +1,22 @@
+// esc_runtime.h -- the context object and helpers shared by the HIP host code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "esc_host.h"
+#include "esc_kernels.h"
+
+struct esc_ctx {
+    int device = 0;
+    int num_cus = 0;
+    unsigned long long *pinned = nullptr;   // 4 KiB of pinned host memory for read-backs
+    int rpt_count = 8;                      // rows per thread of the count kernel
+    int rpt_mat = 8;                        // rows per thread of the materialize kernel
+};
+
+namespace esc {
+
+int hip_fail(hipError_t e, const char *what);
+int occupancy(const void *fn, int block, int dyn_lds);
+ColPtrs slot_ptrs(const esc_table *t, const Program &P);
+
+}  // namespace esc

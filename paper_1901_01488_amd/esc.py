@@ -1,0 +1,338 @@
+"""Thin ctypes binding of libesc.so (include/esc.h).
+
+Argument marshalling only: predicate descriptions are flattened into the
+esc_node / esc_const / esc_udf_insn arrays of the C ABI, torch tensors are
+passed as raw device pointers and streams as hipStream_t handles.  Every step
+of the scan, the batched count and the MLP runs in the library's kernels; if
+the library is not built this module raises on import of the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libesc.so")
+
+INT32, DATE32, FLOAT32 = 0, 1, 2
+OK, ERR_INVALID, ERR_TYPE, ERR_CAPACITY, ERR_ALIGN, ERR_HIP, ERR_OOM, ERR_UNSUPPORTED, ERR_TIMEOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "TYPE", -3: "CAPACITY", -4: "ALIGN", -5: "HIP", -6: "OOM",
+                -7: "UNSUPPORTED", -8: "TIMEOUT"}
+
+AND, OR, EQ, LT, GT, BETWEEN, IN, UDF = range(8)
+_OPS = {"and": AND, "or": OR, "eq": EQ, "lt": LT, "gt": GT, "between": BETWEEN, "in": IN, "udf": UDF}
+U_LOAD, U_ADD, U_SUB, U_MUL, U_MOD, U_AND, U_OR, U_XOR, U_SHL, U_SHR = range(10)
+_UOPS = {"add": U_ADD, "sub": U_SUB, "mul": U_MUL, "mod": U_MOD, "band": U_AND, "bor": U_OR,
+         "bxor": U_XOR, "shl": U_SHL, "shr": U_SHR}
+U_COL, U_CONST = 0, 1
+MLP_NPARAMS = 148481
+MAX_PROJ = 8
+
+
+class EscError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"esc status {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Node(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("col", ctypes.c_int32), ("nchild", ctypes.c_int32),
+                ("cmp", ctypes.c_int32), ("k0", ctypes.c_int32), ("k1", ctypes.c_int32),
+                ("u0", ctypes.c_int32), ("u1", ctypes.c_int32)]
+
+
+class Value(ctypes.Union):
+    _fields_ = [("i", ctypes.c_int32), ("f", ctypes.c_float), ("bits", ctypes.c_uint32)]
+
+
+class Const(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("v", Value)]
+
+
+class UdfInsn(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("src", ctypes.c_int32), ("arg", ctypes.c_int32)]
+
+
+class PredInfo(ctypes.Structure):
+    _fields_ = [("nclauses", ctypes.c_int32), ("ninsns", ctypes.c_int32), ("ncols", ctypes.c_int32),
+                ("constant", ctypes.c_int32), ("col_mask", ctypes.c_uint64)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_01488_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        P = ctypes.POINTER
+        sig = {
+            "esc_last_error": ([], ctypes.c_char_p),
+            "esc_abi_version": ([], ctypes.c_int),
+            "esc_ctx_create": ([ctypes.c_int, P(vp)], ctypes.c_int),
+            "esc_ctx_destroy": ([vp], ctypes.c_int),
+            "esc_ctx_num_cus": ([vp, P(ctypes.c_int)], ctypes.c_int),
+            "esc_table_create": ([i64, ctypes.c_int, vp, vp, P(vp)], ctypes.c_int),
+            "esc_table_destroy": ([vp], ctypes.c_int),
+            "esc_compile_predicate": ([vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, P(vp)], ctypes.c_int),
+            "esc_pred_destroy": ([vp], ctypes.c_int),
+            "esc_pred_get_info": ([vp, P(PredInfo)], ctypes.c_int),
+            "esc_workspace_size": ([vp, ctypes.c_int, P(ctypes.c_size_t)], ctypes.c_int),
+            "esc_workspace_init": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+            "esc_count": ([vp, vp, vp, vp, ctypes.c_size_t, vp, P(u64)], ctypes.c_int),
+            "esc_count_async": ([vp, vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+            "esc_materialize": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, P(u64)],
+                                ctypes.c_int),
+            "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
+            "esc_batch_update": ([vp, vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
+            "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
+            "esc_batch_destroy": ([vp], ctypes.c_int),
+            "esc_featurize": ([vp, vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_mlp_create": ([vp, P(vp)], ctypes.c_int),
+            "esc_mlp_destroy": ([vp], ctypes.c_int),
+            "esc_mlp_set_params": ([vp, vp], ctypes.c_int),
+            "esc_mlp_get_params": ([vp, vp], ctypes.c_int),
+            "esc_mlp_predict": ([vp, vp, i64, vp, vp], ctypes.c_int),
+            "esc_mlp_gradients": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
+            "esc_mlp_train": ([vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_float, vp, vp], ctypes.c_int),
+            "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
+            "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            if not hasattr(L, name):
+                continue
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != OK:
+        raise EscError(rc, lib().esc_last_error().decode())
+    return rc
+
+
+def last_error():
+    return lib().esc_last_error().decode()
+
+
+# ------------------------------------------------------------------ predicates
+
+def flatten(pred, dtypes):
+    """Pre-order esc_node array, typed constants and udf program of a
+    predicate description (see datagen's module docstring)."""
+    nodes, consts, udf = [], [], []
+
+    def const(v, dt):
+        c = Const()
+        c.dtype = dt
+        if dt == FLOAT32:
+            c.v.bits = int(np.asarray(v, np.float32).view(np.uint32))
+        else:
+            c.v.i = int(v)
+        consts.append(c)
+        return len(consts) - 1
+
+    def cmp_consts(op, args, dt):
+        if op == "in":
+            k0 = len(consts)
+            for v in args[0]:
+                const(v, dt)
+            return k0, len(args[0])
+        if op == "between":
+            return const(args[0], dt), const(args[1], dt)
+        return const(args[0], dt), 0
+
+    def udf_prog(e):
+        # left-deep chain: (op, E, leaf) ... (col c) | (const k)
+        chain = []
+        while e[0] not in ("col", "const"):
+            chain.append(e)
+            e = e[1]
+        prog = [(U_LOAD, U_COL if e[0] == "col" else U_CONST, int(e[1]))]
+        for op in reversed(chain):
+            rhs = op[2]
+            if rhs[0] not in ("col", "const"):
+                raise ValueError("udf operands must be columns or constants (left-deep expressions)")
+            prog.append((_UOPS[op[0]], U_COL if rhs[0] == "col" else U_CONST, int(rhs[1])))
+        return prog
+
+    def walk(p):
+        op = p[0]
+        n = Node()
+        n.op = _OPS[op]
+        nodes.append(n)
+        if op in ("and", "or"):
+            n.nchild = len(p[1])
+            for q in p[1]:
+                walk(q)
+            return
+        if op == "udf":
+            prog = udf_prog(p[1])
+            n.u0, n.u1 = len(udf), len(prog)
+            for (o, s, a) in prog:
+                udf.append(UdfInsn(o, s, a))
+            t = p[2]
+            n.cmp = _OPS[t[0]]
+            n.k0, n.k1 = cmp_consts(t[0], t[1:], INT32)
+            return
+        n.col = p[1]
+        dt = dtypes[p[1]] if 0 <= p[1] < len(dtypes) else INT32   # the library rejects the column
+        n.k0, n.k1 = cmp_consts(op, p[2:], dt)
+
+    walk(pred)
+    return ((Node * len(nodes))(*nodes), len(nodes), (Const * max(len(consts), 1))(*consts), len(consts),
+            (UdfInsn * max(len(udf), 1))(*udf), len(udf))
+
+
+class Table:
+    """A table descriptor; device columns (torch tensors of 4-byte dtype) or
+    schema only (cols=None)."""
+
+    def __init__(self, nrows, dtypes, cols=None):
+        self.nrows = int(nrows)
+        self.dtypes = list(dtypes)
+        self.cols = cols
+        dt = np.asarray(self.dtypes, np.int32)
+        self._dt = dt
+        ptrs = None
+        if cols is not None:
+            ptrs = (ctypes.c_void_p * len(cols))(*[c.data_ptr() for c in cols])
+        self._ptrs = ptrs
+        h = ctypes.c_void_p()
+        check(lib().esc_table_create(self.nrows, len(self.dtypes), dt.ctypes.data, ptrs, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_table_destroy(self.h)
+            self.h = None
+
+
+class Pred:
+    def __init__(self, schema: Table, spec):
+        nodes, nn, consts, nc, udf, nu = flatten(spec, schema.dtypes)
+        h = ctypes.c_void_p()
+        check(lib().esc_compile_predicate(schema.h, nodes, nn, consts, nc, udf, nu, ctypes.byref(h)))
+        self.h = h
+        self.spec = spec
+
+    def info(self):
+        i = PredInfo()
+        check(lib().esc_pred_get_info(self.h, ctypes.byref(i)))
+        return {"nclauses": i.nclauses, "ninsns": i.ninsns, "ncols": i.ncols, "constant": i.constant,
+                "col_mask": i.col_mask}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_pred_destroy(self.h)
+            self.h = None
+
+
+def compile_predicate(schema: Table, spec) -> Pred:
+    return Pred(schema, spec)
+
+
+def try_compile(schema: Table, spec):
+    """Status code of compiling spec (no exception)."""
+    nodes, nn, consts, nc, udf, nu = flatten(spec, schema.dtypes)
+    h = ctypes.c_void_p()
+    rc = lib().esc_compile_predicate(schema.h, nodes, nn, consts, nc, udf, nu, ctypes.byref(h))
+    if rc == OK:
+        lib().esc_pred_destroy(h)
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        check(lib().esc_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self._ws = {}
+
+    def num_cus(self):
+        n = ctypes.c_int()
+        check(lib().esc_ctx_num_cus(self.h, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, table: Table, materialize=True, key=None):
+        """A zero-filled device workspace big enough for `table` (cached)."""
+        import torch
+        nb = ctypes.c_size_t()
+        check(lib().esc_workspace_size(table.h, 1 if materialize else 0, ctypes.byref(nb)))
+        k = key if key is not None else "default"
+        ws = self._ws.get(k)
+        if ws is None or ws.numel() < nb.value:
+            ws = torch.zeros(nb.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[k] = ws
+        return ws
+
+    def count(self, table: Table, pred: Pred, ws=None, stream=None) -> int:
+        ws = self.workspace(table, False) if ws is None else ws
+        out = ctypes.c_uint64()
+        check(lib().esc_count(self.h, table.h, pred.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream_handle(stream), ctypes.byref(out)))
+        return out.value
+
+    def count_async(self, table: Table, pred: Pred, dev_out, ws, stream=None):
+        check(lib().esc_count_async(self.h, table.h, pred.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_handle(stream), ctypes.c_void_p(dev_out.data_ptr())))
+
+    def materialize(self, table: Table, pred: Pred, proj, rowids, outs, capacity, ws=None, stream=None,
+                    allow_overflow=False):
+        """Returns the count; rowids/outs are caller-owned device tensors."""
+        ws = self.workspace(table, True) if ws is None else ws
+        pj = np.asarray(proj, np.int32)
+        optrs = (ctypes.c_void_p * max(len(outs), 1))(*[o.data_ptr() for o in outs])
+        out = ctypes.c_uint64()
+        rc = lib().esc_materialize(self.h, table.h, pred.h, pj.ctypes.data if len(pj) else None, len(pj),
+                                   ctypes.c_void_p(rowids.data_ptr()) if rowids is not None else None,
+                                   optrs, int(capacity), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream_handle(stream), ctypes.byref(out))
+        if rc == ERR_CAPACITY and allow_overflow:
+            return out.value
+        check(rc)
+        return out.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_ctx_destroy(self.h)
+            self.h = None
+
+
+def device_table(t, device="cuda:0"):
+    """Table descriptor over device copies of a datagen.Table's columns."""
+    import torch
+    cols = []
+    for c in t.cols:
+        if isinstance(c, np.ndarray):
+            c = torch.from_numpy(np.ascontiguousarray(c))
+        cols.append(c.to(device).contiguous())
+    return Table(t.nrows, t.dtypes, cols)
+
+
+def schema_table(t):
+    return Table(t.nrows, t.dtypes, None)

@@ -283,14 +283,19 @@ EDGE_CASES = [
 ]
 
 
+def edge_pred(pred, t):
+    """EDGE_CASES entries with float32 constants on the float column."""
+    if pred[0] == "udf" or t.dtypes[pred[1]] != dg.FLOAT32:
+        return pred
+    if pred[0] == "in":
+        return ("in", pred[1], [np.float32(v) for v in pred[2]])
+    return (pred[0], pred[1]) + tuple(np.float32(v) for v in pred[2:])
+
+
 @pytest.mark.parametrize("pred,want", EDGE_CASES)
 def test_edge_values(pred, want):
     t = dg.table_edge_floats()
-    p = tuple(np.float32(v) if (t.dtypes[pred[1]] == dg.FLOAT32 and isinstance(v, float)) else v
-              for v in pred) if pred[0] not in ("in", "udf") else pred
-    if pred[0] == "in" and t.dtypes[pred[1]] == dg.FLOAT32:
-        p = ("in", pred[1], [np.float32(v) for v in pred[2]])
-    assert scan.count(t, p) == want
+    assert scan.count(t, edge_pred(pred, t)) == want
 
 
 # ----------------------------------------------------------- golden example
