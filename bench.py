@@ -57,7 +57,7 @@ def cpu_baseline(t_host, preds, budget_s=25.0):
     predicates, count only; scaled to GB/s of algorithmic bytes."""
     from oracle import scan
     from paper_1901_01488_amd import datagen as dg
-    n = min(t_host.nrows, 24_000_000)
+    n = t_host.nrows
     sub = dg.Table("sample", n, t_host.dtypes, [c[:n] for c in t_host.cols]).host()
     t0 = time.perf_counter()
     nbytes = 0
@@ -164,6 +164,9 @@ def main():
     extras = {}
     if not args.no_extras:
         extras.update(plain_latency(ctx, esc, dg, torch, dev))
+        del dt, t, rowids, outs
+        torch.cuda.empty_cache()
+        extras.update(batched_vs_plain(ctx, esc, dg, torch, dev))
 
     line = {
         "metric": "ESC scan GB/s vs HBM peak; predicates/s batched vs plain; p50/p99 ms/query",
@@ -179,6 +182,63 @@ def main():
         line["cpu_baseline"] = cpu_baseline(t, preds)
     line["extras"] = extras
     print(json.dumps(line), flush=True)
+
+
+def batched_vs_plain(ctx, esc, dg, torch, dev, reps=10):
+    """256 selectivity sub-queries over 8 tables of 10K..200M rows: one
+    autotuned graph launch of the batched kernel vs 256 plain count calls
+    (each synchronous, and all queued then one synchronisation)."""
+    log("batched workload: generating tables")
+    tabs = dg.tables_batched(device=dev)
+    preds, owner = dg.preds_batched(tabs)
+    dts = [esc.Table(t.nrows, t.dtypes, t.cols) for t in tabs]
+    cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    torch.cuda.synchronize()
+    log("batched workload: autotune")
+    t0 = time.perf_counter()
+    b = esc.Batch(ctx, dts, cps, owner, autotune=True)
+    tune_s = time.perf_counter() - t0
+    got = b.count()
+    ws = [ctx.workspace(d, False, key=("bt", i)) for i, d in enumerate(dts)]
+    plain = [ctx.count(dts[o], p, ws=ws[o]) for p, o in zip(cps, owner)]
+    assert got.tolist() == plain
+    tb = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        b.count()
+        tb.append(time.perf_counter() - a)
+    ts = []
+    for _ in range(3):
+        a = time.perf_counter()
+        for p, o in zip(cps, owner):
+            ctx.count(dts[o], p, ws=ws[o])
+        ts.append(time.perf_counter() - a)
+    dout = torch.zeros(len(cps), dtype=torch.int64, device=dev)
+    aws = ctx.workspace(dts[0], False, key="ba")   # one stream: launches run in order
+    ta = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i, (p, o) in enumerate(zip(cps, owner)):
+            ctx.count_async(dts[o], p, dout[i:i + 1], aws)
+        torch.cuda.synchronize()
+        ta.append(time.perf_counter() - a)
+    assert dout.cpu().tolist() == plain
+    n = len(cps)
+    tbm, tsm, tam = float(np.median(tb)), float(np.median(ts)), float(np.median(ta))
+    bytes_batched = 0
+    for ti, t in enumerate(tabs):
+        used = set()
+        for p, o in zip(preds, owner):
+            if o == ti:
+                used |= pred_columns(p)
+        bytes_batched += len(used) * t.nrows * 4
+    return {"batched_256_predicates_per_s": round(n / tbm, 1),
+            "plain_sync_predicates_per_s": round(n / tsm, 1),
+            "plain_async_predicates_per_s": round(n / tam, 1),
+            "batched_speedup_vs_best_plain": round(min(tsm, tam) / tbm, 2),
+            "batched_ms": round(tbm * 1e3, 3), "batched_GBps_distinct_columns": round(bytes_batched / tbm / 1e9, 1),
+            "batched_opts": b.opts(), "autotune_s": round(tune_s, 2)}
 
 
 def plain_latency(ctx, esc, dg, torch, dev, reps=300):

@@ -1,0 +1,549 @@
+// esc_batch.hip -- batched exact selectivity computation: many COUNT(*)
+// sub-queries over several tables in one persistent kernel, launched from a
+// hipGraph.
+//
+// The paper runs one selectivity sub-query per table with a selection
+// (Section 2: "the same procedure is applied to each table having selection
+// predicates").  Here all of them run at once: the predicates of a table are
+// packed into groups whose column union fits the register slots; a group's
+// rows are cut into chunks, and the (group, chunk) work items sit in a list
+// ordered by decreasing cost.  Each block of the persistent grid pops items
+// from an atomic counter, loads every column of the group once per tile and
+// runs every member predicate on the registers.  Per-wave counts accumulate
+// in LDS and reach the global u64 counters with one atomic per predicate per
+// item.  Counts are exact and independent of the order of the additions.
+//
+// The launch (zero counters -> persistent kernel -> copy of the counts to
+// pinned host memory) is captured once into a hipGraph; a count is one
+// graph launch and one stream synchronisation.  Block shape, rows per thread,
+// group size and chunk length are chosen by timing candidate plans on the
+// actual tables (an autotuner with an in-process cache and an optional file).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "esc_device.h"
+#include "esc_host.h"
+#include "esc_kernels.h"
+#include "esc_runtime.h"
+
+namespace esc {
+
+constexpr int kMaxGroup = 1024;   // predicates evaluated per pass over a chunk
+
+struct BatchGroup {
+    const uint32_t *cols[kMaxSlots];
+    int32_t K;
+    int32_t npred;
+    int32_t pbegin;   // first program / predicate id of the group
+    int32_t pad;
+};
+
+struct BatchItem {
+    int32_t group;
+    int32_t r0, r1;
+    int32_t pad;
+};
+
+template <int K, int RPT>
+__device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
+                                         uint32_t (*s_cnt)[kScanBlock / 64])
+{
+    constexpr int TILE = kScanBlock * RPT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    ColPtrs cp{};
+#pragma unroll
+    for (int c = 0; c < K; c++) cp.p[c] = g.cols[c];
+    const int npred = g.npred;
+    for (int64_t base = it.r0; base < it.r1; base += TILE) {
+        uint32_t v[K][RPT];
+        load_vals<K, RPT>(cp, base, it.r1, v);
+        const bool full = base + TILE <= it.r1;
+        for (int i = 0; i < npred; i++) {
+            uint64_t acc[RPT];
+            // the valid-row masks are rebuilt per predicate (cheap) rather than
+            // kept live across the program, to spare scalar registers
+#pragma unroll
+            for (int r = 0; r < RPT; r++) acc[r] = full ? ~0ull : __ballot(row_of(base, r) < it.r1);
+            run_program<K, RPT>(progs[g.pbegin + i], v, acc);
+            uint32_t c = 0;
+#pragma unroll
+            for (int r = 0; r < RPT; r++) c += (uint32_t)__popcll(acc[r]);
+            if (lane == 0) s_cnt[i][wave] += c;
+        }
+    }
+}
+
+template <int RPT>
+__global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
+                                                           const BatchItem *__restrict__ items, int nitems,
+                                                           const Program *__restrict__ progs,
+                                                           const int32_t *__restrict__ pred_ids,
+                                                           unsigned long long *counts, unsigned int *queue)
+{
+    constexpr int NW = kScanBlock / 64;
+    __shared__ uint32_t s_cnt[kMaxGroup][NW];
+    __shared__ int s_item;
+    for (int i = threadIdx.x; i < kMaxGroup * NW; i += kScanBlock) (&s_cnt[0][0])[i] = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= nitems) break;
+        const BatchItem it = items[item];
+        const BatchGroup &g = groups[it.group];
+        switch (g.K) {
+        case 1: run_item<1, RPT>(g, it, progs, s_cnt); break;
+        case 2: run_item<2, RPT>(g, it, progs, s_cnt); break;
+        case 3: run_item<3, RPT>(g, it, progs, s_cnt); break;
+        case 4: run_item<4, RPT>(g, it, progs, s_cnt); break;
+        case 5: run_item<5, RPT>(g, it, progs, s_cnt); break;
+        case 6: run_item<6, RPT>(g, it, progs, s_cnt); break;
+        case 7: run_item<7, RPT>(g, it, progs, s_cnt); break;
+        default: run_item<8, RPT>(g, it, progs, s_cnt); break;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < g.npred; i += kScanBlock) {
+            unsigned long long s = 0;
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                s += s_cnt[i][w];
+                s_cnt[i][w] = 0;
+            }
+            if (s) atomicAdd(&counts[pred_ids[g.pbegin + i]], s);
+        }
+        __syncthreads();
+    }
+}
+
+typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, int, const Program *, const int32_t *,
+                        unsigned long long *, unsigned int *);
+
+static BatchFn batch_fn(int rpt) { return rpt == 4 ? batch_kernel<4> : batch_kernel<8>; }
+
+__global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counts[i] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *queue = 0u;
+}
+
+}  // namespace esc
+
+using namespace esc;
+
+struct TableInfo {
+    int64_t nrows;
+    std::vector<int32_t> dtypes;
+    std::vector<const void *> cols;
+};
+
+struct Plan {
+    std::vector<BatchGroup> groups;
+    std::vector<BatchItem> items;
+    std::vector<Program> progs;
+    std::vector<int32_t> pred_ids;
+};
+
+struct esc_batch {
+    esc_ctx *ctx = nullptr;
+    std::vector<TableInfo> tables;
+    std::vector<int32_t> pred_table;
+    std::vector<Program> src;            // compiled programs as given
+    std::vector<int> constant;           // 0: scanned; 1: always true; -1: always false or empty table
+    esc_batch_opts opts{};
+    int nkernel = 0;                     // predicates evaluated by the kernel
+    // device state
+    BatchGroup *d_groups = nullptr;
+    BatchItem *d_items = nullptr;
+    Program *d_progs = nullptr;
+    int32_t *d_pred_ids = nullptr;
+    unsigned long long *d_counts = nullptr;
+    unsigned int *d_queue = nullptr;
+    size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
+    unsigned long long *h_counts = nullptr;   // pinned
+    int nitems = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+int hipchk(hipError_t e, const char *what) { return e == hipSuccess ? ESC_OK : hip_fail(e, what); }
+
+int tile_rows(int rpt) { return kScanBlock * rpt; }
+
+// Remaps the slots of program P (its own slot order) onto the group's slots.
+Program remap(const Program &P, const int *gslot_of_col, int K, const int *gcols)
+{
+    Program Q = P;
+    for (int i = 0; i < P.ninsn; i++) {
+        Insn &I = Q.insn[i];
+        const bool udf_op = I.op >= U_LOAD;
+        const bool reads_col = udf_op ? !(I.flags & F_CONST) : !(I.flags & F_SRC_UDF);
+        if (reads_col) I.src = (uint8_t)gslot_of_col[P.slot_col[I.src]];
+    }
+    Q.nslots = K;
+    for (int s = 0; s < kMaxSlots; s++) Q.slot_col[s] = s < K ? gcols[s] : 0;
+    return Q;
+}
+
+int build_plan(const esc_batch *b, const esc_batch_opts &o, Plan &plan)
+{
+    plan = Plan{};
+    const int tile = tile_rows(o.rows_per_thread);
+    int64_t chunk = o.chunk_rows > 0 ? o.chunk_rows : 262144;
+    chunk = (chunk + tile - 1) / tile * tile;
+    const int gmax = o.group > 0 ? std::min(o.group, kMaxGroup) : kMaxGroup;
+    struct Cost { int64_t cost; BatchItem it; };
+    std::vector<Cost> items;
+    for (size_t t = 0; t < b->tables.size(); t++) {
+        const TableInfo &T = b->tables[t];
+        std::vector<int> members;
+        for (size_t p = 0; p < b->pred_table.size(); p++)
+            if (b->pred_table[p] == (int)t && b->constant[p] == 0) members.push_back((int)p);
+        size_t i = 0;
+        while (i < members.size()) {
+            int gslot[64];
+            for (int c = 0; c < 64; c++) gslot[c] = -1;
+            int gcols[kMaxSlots];
+            int K = 0;
+            std::vector<int> mem;
+            while (i < members.size() && (int)mem.size() < gmax) {
+                const Program &P = b->src[members[i]];
+                int add = 0;
+                for (int s = 0; s < P.nslots; s++) add += gslot[P.slot_col[s]] < 0;
+                if (K + add > kMaxSlots) break;
+                for (int s = 0; s < P.nslots; s++)
+                    if (gslot[P.slot_col[s]] < 0) { gslot[P.slot_col[s]] = K; gcols[K++] = P.slot_col[s]; }
+                mem.push_back(members[i]);
+                i++;
+            }
+            BatchGroup g{};
+            g.K = K > 0 ? K : 1;
+            if (K == 0) gcols[0] = 0;
+            for (int s = 0; s < g.K; s++) g.cols[s] = (const uint32_t *)T.cols[gcols[s]];
+            g.npred = (int)mem.size();
+            g.pbegin = (int)plan.progs.size();
+            for (int p : mem) {
+                plan.progs.push_back(remap(b->src[p], gslot, g.K, gcols));
+                plan.pred_ids.push_back(p);
+            }
+            const int gid = (int)plan.groups.size();
+            plan.groups.push_back(g);
+            for (int64_t r0 = 0; r0 < T.nrows; r0 += chunk) {
+                const int64_t r1 = std::min<int64_t>(T.nrows, r0 + chunk);
+                BatchItem it{gid, (int32_t)r0, (int32_t)r1, 0};
+                items.push_back({(r1 - r0) * (int64_t)mem.size() * (K + 1), it});
+            }
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Cost &a, const Cost &c) { return a.cost > c.cost; });
+    for (auto &c : items) plan.items.push_back(c.it);
+    return ESC_OK;
+}
+
+template <typename T>
+int ensure(T *&ptr, size_t &cap, size_t n)
+{
+    if (n <= cap && ptr) return ESC_OK;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const size_t m = std::max<size_t>(n, 1);
+    hipError_t e = hipMalloc((void **)&ptr, m * sizeof(T));
+    if (e != hipSuccess) return fail(ESC_ERR_OOM, "hipMalloc of %zu bytes: %s", m * sizeof(T), hipGetErrorString(e));
+    cap = m;
+    return ESC_OK;
+}
+
+void destroy_graph(esc_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Uploads a plan and captures zero -> kernel -> copy into a graph.
+int install(esc_batch *b, const esc_batch_opts &o)
+{
+    Plan plan;
+    int rc = build_plan(b, o, plan);
+    if (rc) return rc;
+    if ((rc = ensure(b->d_groups, b->cap_groups, plan.groups.size()))) return rc;
+    if ((rc = ensure(b->d_items, b->cap_items, plan.items.size()))) return rc;
+    if ((rc = ensure(b->d_progs, b->cap_progs, plan.progs.size()))) return rc;
+    if ((rc = ensure(b->d_pred_ids, b->cap_ids, plan.pred_ids.size()))) return rc;
+    hipStream_t s = b->cap_stream;
+    if ((rc = hipchk(hipMemcpyAsync(b->d_groups, plan.groups.data(), plan.groups.size() * sizeof(BatchGroup),
+                                    hipMemcpyHostToDevice, s), "upload groups"))) return rc;
+    if ((rc = hipchk(hipMemcpyAsync(b->d_items, plan.items.data(), plan.items.size() * sizeof(BatchItem),
+                                    hipMemcpyHostToDevice, s), "upload items"))) return rc;
+    if ((rc = hipchk(hipMemcpyAsync(b->d_progs, plan.progs.data(), plan.progs.size() * sizeof(Program),
+                                    hipMemcpyHostToDevice, s), "upload programs"))) return rc;
+    if ((rc = hipchk(hipMemcpyAsync(b->d_pred_ids, plan.pred_ids.data(), plan.pred_ids.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s), "upload ids"))) return rc;
+    if ((rc = hipchk(hipStreamSynchronize(s), "upload sync"))) return rc;
+    b->nitems = (int)plan.items.size();
+    BatchFn fn = batch_fn(o.rows_per_thread);
+    int occ = occupancy((const void *)fn, kScanBlock, 0);
+    int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
+    int64_t grid = (int64_t)b->ctx->num_cus * bpc;
+    if (grid > b->nitems) grid = b->nitems;
+    if (grid < 1) grid = 1;
+    b->grid = (int)grid;
+    destroy_graph(b);
+    const int npreds = (int)b->pred_table.size();
+    if ((rc = hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture"))) return rc;
+    hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(1, std::min(64, (npreds + 255) / 256))), dim3(256), 0, s,
+                       b->d_counts, npreds, b->d_queue);
+    if (b->nitems > 0)
+        hipLaunchKernelGGL(fn, dim3(b->grid), dim3(kScanBlock), 0, s, b->d_groups, b->d_items, b->nitems,
+                           b->d_progs, b->d_pred_ids, b->d_counts, b->d_queue);
+    (void)hipMemcpyAsync(b->h_counts, b->d_counts, std::max(npreds, 1) * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    b->graph = g;
+    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
+    b->opts = o;
+    b->opts.blocks_per_cu = bpc;
+    return ESC_OK;
+}
+
+int run(esc_batch *b, hipStream_t s, uint64_t *out)
+{
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (out) {
+        for (size_t p = 0; p < b->pred_table.size(); p++) {
+            if (b->constant[p] == 1) out[p] = (uint64_t)b->tables[b->pred_table[p]].nrows;
+            else if (b->constant[p] == -1) out[p] = 0;
+            else out[p] = b->h_counts[p];
+        }
+    }
+    return ESC_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, esc_batch_opts> g_tune_cache;
+
+std::string tune_key(const esc_batch *b)
+{
+    std::string k = "cus=" + std::to_string(b->ctx->num_cus);
+    for (size_t t = 0; t < b->tables.size(); t++) {
+        int np = 0, ni = 0;
+        for (size_t p = 0; p < b->pred_table.size(); p++)
+            if (b->pred_table[p] == (int)t) { np++; ni += b->src[p].ninsn; }
+        k += ";" + std::to_string(b->tables[t].nrows) + "x" + std::to_string(b->tables[t].dtypes.size()) + ":" +
+             std::to_string(np) + "/" + std::to_string(ni);
+    }
+    return k;
+}
+
+void load_tune_file()
+{
+    static bool done = false;
+    if (done) return;
+    done = true;
+    const char *path = getenv("ESC_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[4096];
+    esc_batch_opts o{};
+    while (fscanf(f, "%4095s %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
+                  &o.blocks_per_cu) == 6)
+        g_tune_cache[key] = o;
+    fclose(f);
+}
+
+void save_tune(const std::string &key, const esc_batch_opts &o)
+{
+    const char *path = getenv("ESC_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows, o.blocks_per_cu);
+    fclose(f);
+}
+
+// Times candidate plans on the batch's own tables and keeps the fastest;
+// every candidate's counts must agree (a free consistency check).
+int autotune(esc_batch *b, hipStream_t s)
+{
+    const std::string key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        load_tune_file();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return install(b, it->second);
+    }
+    const int npreds = (int)b->pred_table.size();
+    std::vector<uint64_t> ref(npreds), got(npreds);
+    bool have_ref = false;
+    float best = 1e30f;
+    esc_batch_opts bo{};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ESC_ERR_HIP, "hipEventCreate failed");
+    int rc = ESC_OK;
+    const int rpts[] = {8, 4};
+    const int groups[] = {0, 16, 8};
+    const int chunks[] = {1 << 17, 1 << 19, 1 << 21};
+    for (int rpt : rpts)
+        for (int grp : groups)
+            for (int ch : chunks) {
+                esc_batch_opts o{};
+                o.block = kScanBlock;
+                o.rows_per_thread = rpt;
+                o.group = grp;
+                o.chunk_rows = ch;
+                if ((rc = install(b, o))) goto done;
+                if ((rc = run(b, s, got.data()))) goto done;
+                if (!have_ref) { ref = got; have_ref = true; }
+                else if (ref != got) { rc = fail(ESC_ERR_HIP, "autotune: candidate plans disagree on a count"); goto done; }
+                float tmin = 1e30f;
+                for (int rep = 0; rep < 3; rep++) {
+                    (void)hipEventRecord(e0, s);
+                    (void)hipGraphLaunch(b->exec, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    tmin = std::min(tmin, ms);
+                }
+                if (tmin < best) { best = tmin; bo = b->opts; }
+            }
+    rc = install(b, bo);
+    if (!rc) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = b->opts;
+        save_tune(key, b->opts);
+    }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int set_preds(esc_batch *b, const esc_pred *const *preds, int npreds)
+{
+    b->src.resize(npreds);
+    b->constant.assign(npreds, 0);
+    for (int p = 0; p < npreds; p++) {
+        if (!preds[p]) return fail(ESC_ERR_INVALID, "predicate %d is null", p);
+        const TableInfo &T = b->tables[b->pred_table[p]];
+        if (preds[p]->schema_dtypes != T.dtypes)
+            return fail(ESC_ERR_INVALID, "predicate %d was compiled for another schema than table %d", p, b->pred_table[p]);
+        b->src[p] = preds[p]->prog;
+        const int fl = preds[p]->prog.flags;
+        if (T.nrows == 0 || (fl & P_ALWAYS_FALSE)) b->constant[p] = -1;
+        else if (fl & P_ALWAYS_TRUE) b->constant[p] = 1;
+    }
+    return ESC_OK;
+}
+
+void free_batch(esc_batch *b)
+{
+    destroy_graph(b);
+    if (b->d_groups) (void)hipFree(b->d_groups);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_progs) (void)hipFree(b->d_progs);
+    if (b->d_pred_ids) (void)hipFree(b->d_pred_ids);
+    if (b->d_counts) (void)hipFree(b->d_counts);
+    if (b->d_queue) (void)hipFree(b->d_queue);
+    if (b->h_counts) (void)hipHostFree(b->h_counts);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, const esc_pred *const *preds,
+                     const int32_t *pred_table, int npreds, const esc_batch_opts *opts, void *stream,
+                     esc_batch **out)
+{
+    if (!ctx || !tables || !preds || !pred_table || !out) return fail(ESC_ERR_INVALID, "null argument");
+    if (ntables <= 0 || npreds <= 0) return fail(ESC_ERR_INVALID, "empty batch");
+    esc_batch *b = new (std::nothrow) esc_batch;
+    if (!b) return fail(ESC_ERR_OOM, "out of host memory");
+    b->ctx = ctx;
+    (void)hipSetDevice(ctx->device);
+    int rc = ESC_OK;
+    for (int t = 0; t < ntables; t++) {
+        if (!tables[t] || !tables[t]->has_data()) { free_batch(b); return fail(ESC_ERR_INVALID, "table %d has no device columns", t); }
+        b->tables.push_back({tables[t]->nrows, tables[t]->dtypes, tables[t]->cols});
+    }
+    b->pred_table.assign(pred_table, pred_table + npreds);
+    for (int p = 0; p < npreds; p++)
+        if (pred_table[p] < 0 || pred_table[p] >= ntables) { free_batch(b); return fail(ESC_ERR_INVALID, "pred_table[%d] out of range", p); }
+    if ((rc = set_preds(b, preds, npreds))) { free_batch(b); return rc; }
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) { free_batch(b); return hip_fail(e, "stream"); }
+    if ((e = hipMalloc((void **)&b->d_counts, npreds * sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_queue, 256)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->h_counts, npreds * sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess) {
+        free_batch(b);
+        return fail(ESC_ERR_OOM, "batch allocation: %s", hipGetErrorString(e));
+    }
+    esc_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.rows_per_thread != 4) o.rows_per_thread = 8;
+    o.block = kScanBlock;
+    if (opts && opts->autotune) rc = autotune(b, (hipStream_t)stream);
+    else rc = install(b, o);
+    if (rc) { free_batch(b); return rc; }
+    *out = b;
+    return ESC_OK;
+}
+
+int esc_batch_update(esc_batch *b, const esc_pred *const *preds, int npreds, void *stream)
+{
+    (void)stream;
+    if (!b || !preds) return fail(ESC_ERR_INVALID, "null argument");
+    if (npreds != (int)b->pred_table.size()) return fail(ESC_ERR_INVALID, "update must keep the number of predicates");
+    (void)hipSetDevice(b->ctx->device);
+    int rc = set_preds(b, preds, npreds);
+    if (rc) return rc;
+    return install(b, b->opts);
+}
+
+int esc_batch_count(esc_batch *b, void *stream, uint64_t *out_counts)
+{
+    if (!b || !out_counts) return fail(ESC_ERR_INVALID, "null argument");
+    (void)hipSetDevice(b->ctx->device);
+    return run(b, (hipStream_t)stream, out_counts);
+}
+
+int esc_batch_get_opts(const esc_batch *b, esc_batch_opts *out)
+{
+    if (!b || !out) return fail(ESC_ERR_INVALID, "null argument");
+    *out = b->opts;
+    return ESC_OK;
+}
+
+int esc_batch_destroy(esc_batch *b)
+{
+    if (!b) return ESC_OK;
+    (void)hipSetDevice(b->ctx->device);
+    free_batch(b);
+    return ESC_OK;
+}
+
+}  // extern "C"

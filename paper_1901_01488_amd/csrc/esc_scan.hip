@@ -26,241 +26,37 @@
 #include <new>
 #include <type_traits>
 
+#include "esc_device.h"
 #include "esc_host.h"
 #include "esc_kernels.h"
 
 namespace esc {
 
-// ------------------------------------------------------------------ device helpers
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ float as_f(uint32_t u) { return __uint_as_float(u); }
-
-template <int K, int C = 0, typename F>
-__device__ __forceinline__ void for_slot(int s, F &&f)
-{
-    if constexpr (C < K) {
-        if (s == C) f(std::integral_constant<int, C>{});
-        else for_slot<K, C + 1>(s, f);
-    }
-}
-
-// Lane masks of one test, folded straight into the clause state: MODE 0 ORs
-// into the open clause cm, MODE 1 (a one-leaf clause) ANDs into acc.
-template <int MODE, int RPT, typename T>
-__device__ __forceinline__ void fold(uint64_t (&acc)[RPT], uint64_t (&cm)[RPT], T &&test)
-{
-#pragma unroll
-    for (int r = 0; r < RPT; r++) {
-        const uint64_t m = __ballot(test(r));
-        if (MODE == 0) cm[r] |= m;
-        else acc[r] &= m;
-    }
-}
-
-template <int MODE, int RPT>
-__device__ __forceinline__ void run_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT],
-                                         uint64_t (&acc)[RPT], uint64_t (&cm)[RPT])
-{
-    switch (I.op) {
-    case T_RANGE_I32: {
-        const uint32_t lo = (uint32_t)I.a, span = (uint32_t)I.b;
-        fold<MODE>(acc, cm, [&](int r) { return x[r] - lo <= span; });
-        break;
-    }
-    case T_RANGE_F32: {
-        const float lo = as_f((uint32_t)I.a), hi = as_f((uint32_t)I.b);
-        fold<MODE>(acc, cm, [&](int r) { const float f = as_f(x[r]); return lo <= f && f <= hi; });
-        break;
-    }
-    case T_BITSET: {
-        const uint32_t lo = (uint32_t)I.a;
-        const uint64_t bits = (uint64_t)(uint32_t)I.b | ((uint64_t)(uint32_t)I.c << 32);
-        fold<MODE>(acc, cm, [&](int r) {
-            const uint32_t d = x[r] - lo;
-            return d < 64u && ((bits >> (d & 63u)) & 1ull);
-        });
-        break;
-    }
-    case T_IN_I32:
-    case T_IN_F32: {
-        // OR over the set members per row, then fold once
-        uint64_t m[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; r++) m[r] = 0;
-        const bool fl = I.op == T_IN_F32;
-        for (int k = 0; k < I.b; k++) {
-            const uint32_t kv = kpool[I.a + k];
-            if (fl) {
-                const float kf = as_f(kv);
-#pragma unroll
-                for (int r = 0; r < RPT; r++) m[r] |= __ballot(as_f(x[r]) == kf);
-            } else {
-#pragma unroll
-                for (int r = 0; r < RPT; r++) m[r] |= __ballot(x[r] == kv);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-            if (MODE == 0) cm[r] |= m[r];
-            else acc[r] &= m[r];
-        }
-        break;
-    }
-    default:
-        if (MODE == 1) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) acc[r] = 0;
-        }
-    }
-}
-
-template <int K, int RPT, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ void run_udf(const Insn &I, const uint32_t (&v)[KK][RPT], uint32_t (&u)[RPT])
-{
-    uint32_t o[RPT];
-    if (I.flags & F_CONST) {
-#pragma unroll
-        for (int r = 0; r < RPT; r++) o[r] = (uint32_t)I.a;
-    } else {
-        for_slot<K>(I.src, [&](auto C) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) o[r] = v[C][r];
-        });
-    }
-    switch (I.op) {
-    case U_LOAD:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] = o[r];
-        break;
-    case U_ADD:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] += o[r];
-        break;
-    case U_SUB:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] -= o[r];
-        break;
-    case U_MUL:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] *= o[r];
-        break;
-    case U_MOD: {
-        const int32_t m = I.a;   // > 0, checked by the compiler
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] = (uint32_t)((int32_t)u[r] % m);
-        break;
-    }
-    case U_AND:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] &= o[r];
-        break;
-    case U_OR:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] |= o[r];
-        break;
-    case U_XOR:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] ^= o[r];
-        break;
-    case U_SHL:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] <<= (uint32_t)I.a;
-        break;
-    case U_SHR:
-#pragma unroll
-        for (int r = 0; r < RPT; r++) u[r] = (uint32_t)((int32_t)u[r] >> I.a);
-        break;
-    }
-}
-
-// Runs the program on the loaded slots; acc[r] enters as the mask of valid
-// rows and leaves as the mask of qualifying rows.
-template <int K, int RPT, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ void run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint64_t (&acc)[RPT])
-{
-    uint64_t cm[RPT];
-    uint32_t u[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; r++) { cm[r] = 0; u[r] = 0; }
-    const int n = P.ninsn;
-    for (int i = 0; i < n; i++) {
-        const Insn I = P.insn[i];
-        if (I.op >= U_LOAD) {
-            run_udf<K, RPT>(I, v, u);
-            continue;
-        }
-        const bool single = I.flags & F_SINGLE;
-        if (I.flags & F_SRC_UDF) {
-            if (single) run_test<1, RPT>(I, P.kpool, u, acc, cm);
-            else run_test<0, RPT>(I, P.kpool, u, acc, cm);
-        } else if (single) {
-            for_slot<K>(I.src, [&](auto C) { run_test<1, RPT>(I, P.kpool, v[C], acc, cm); });
-        } else {
-            for_slot<K>(I.src, [&](auto C) { run_test<0, RPT>(I, P.kpool, v[C], acc, cm); });
-        }
-        if (!single && (I.flags & F_END_CLAUSE)) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) { acc[r] &= cm[r]; cm[r] = 0; }
-        }
-    }
-}
-
-// Row of slot r for this thread: base + (j*256 + tid)*4 + e with r = 4j + e.
-__device__ __forceinline__ int64_t row_of(int64_t base, int r)
-{
-    return base + ((int64_t)(r >> 2) * kScanBlock + threadIdx.x) * 4 + (r & 3);
-}
-
-template <int K, int RPT, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ void load_tile(const ColPtrs &cp, int64_t base, int64_t n, uint32_t (&v)[KK][RPT],
-                                          uint64_t (&acc)[RPT])
-{
-    constexpr int TILE = kScanBlock * RPT;
-    if (base + TILE <= n) {
-#pragma unroll
-        for (int j = 0; j < RPT / 4; j++) {
-            const int64_t idx = base + ((int64_t)j * kScanBlock + threadIdx.x) * 4;
-#pragma unroll
-            for (int c = 0; c < K; c++) {
-                const u32x4 q = __builtin_nontemporal_load((const u32x4 *)(cp.p[c] + idx));
-                v[c][4 * j + 0] = q.x;
-                v[c][4 * j + 1] = q.y;
-                v[c][4 * j + 2] = q.z;
-                v[c][4 * j + 3] = q.w;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RPT; r++) acc[r] = ~0ull;
-    } else {
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-            const int64_t row = row_of(base, r);
-            const bool ok = row < n;
-#pragma unroll
-            for (int c = 0; c < K; c++) v[c][r] = ok ? cp.p[c][row] : 0u;
-            acc[r] = __ballot(ok);
-        }
-    }
-}
-
 // ------------------------------------------------------------------ count
 
+// Grid-stride over tiles with a two-deep register pipeline: the loads of
+// the block's next tile are in flight while the current one is evaluated.
 template <int K, int RPT>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            WsHeader *ws, unsigned long long *out)
 {
     constexpr int TILE = kScanBlock * RPT;
+    constexpr int KK = K > 0 ? K : 1;
     const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t step = gridDim.x;
     uint32_t cnt = 0;   // wave-uniform
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        uint32_t v[K > 0 ? K : 1][RPT];
-        uint64_t acc[RPT];
-        load_tile<K, RPT>(cp, t * TILE, n, v, acc);
-        run_program<K, RPT>(P, v, acc);
-#pragma unroll
-        for (int r = 0; r < RPT; r++) cnt += (uint32_t)__popcll(acc[r]);
+    uint32_t va[KK][RPT], vb[KK][RPT];
+    int64_t t = blockIdx.x;
+    if (t < ntiles) load_vals<K, RPT>(cp, t * TILE, n, va);
+    while (t < ntiles) {
+        const int64_t t1 = t + step;
+        if (t1 < ntiles) load_vals<K, RPT>(cp, t1 * TILE, n, vb);
+        cnt += eval_count<K, RPT>(P, va, t * TILE, n);
+        if (t1 >= ntiles) break;
+        const int64_t t2 = t1 + step;
+        if (t2 < ntiles) load_vals<K, RPT>(cp, t2 * TILE, n, va);
+        cnt += eval_count<K, RPT>(P, vb, t1 * TILE, n);
+        t = t2;
     }
     __shared__ uint32_t s_cnt[kScanBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -346,6 +142,92 @@ __device__ unsigned long long lookback(unsigned long long *status, int tile, uns
     return excl;
 }
 
+// Evaluates one loaded tile, obtains its exclusive prefix by look-back and
+// writes its qualifying rows.  Called by the whole block.
+template <int K, int RPT, int KK = (K > 0 ? K : 1)>
+__device__ __forceinline__ void compact_tile(const Program &P, const uint32_t (&v)[KK][RPT], int tile, int ntiles,
+                                             int64_t n, const ProjArgs &pa, int32_t *rowids,
+                                             unsigned long long cap, WsHeader *ws, unsigned long long *status,
+                                             uint32_t (*s_wcnt)[kScanBlock / 64], unsigned long long *s_excl)
+{
+    constexpr int TILE = kScanBlock * RPT;
+    constexpr int NW = kScanBlock / 64;
+    constexpr int NJ = RPT / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)tile * TILE;
+    uint64_t acc[RPT];
+    valid_masks<RPT>(base, n, acc);
+    run_program<K, RPT>(P, v, acc);
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const uint32_t c = (uint32_t)(__popcll(acc[4 * j]) + __popcll(acc[4 * j + 1]) +
+                                      __popcll(acc[4 * j + 2]) + __popcll(acc[4 * j + 3]));
+        if (lane == 0) s_wcnt[j][wave] = c;
+    }
+    __syncthreads();
+    // offset of (chunk j, this wave) inside the tile: chunk-major, then wave
+    uint32_t off[NJ];
+    uint32_t total = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; j++)
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            if (w == wave) off[j] = total;
+            total += s_wcnt[j][w];
+        }
+    if (wave == 0) {
+        const unsigned long long ex = lookback(status, tile, total, ws);
+        if (lane == 0) {
+            *s_excl = ex;
+            if (tile == ntiles - 1) ws->result = ex + total;
+        }
+    }
+    __syncthreads();
+    const unsigned long long excl = *s_excl;
+    if (total == 0) return;
+    // rank of each selected row of this lane: lanes below first, then e
+    unsigned long long pos[RPT];
+    bool sel[RPT];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        unsigned long long p = excl + off[j];
+#pragma unroll
+        for (int e = 0; e < 4; e++) p += (unsigned long long)__popcll(acc[4 * j + e] & lt);
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const bool bit = (acc[4 * j + e] >> lane) & 1ull;
+            pos[4 * j + e] = p;
+            sel[4 * j + e] = bit && p < cap;
+            p += bit ? 1 : 0;
+        }
+    }
+    if (rowids) {
+#pragma unroll
+        for (int r = 0; r < RPT; r++)
+            if (sel[r]) rowids[pos[r]] = (int32_t)row_of(base, r);
+    }
+    for (int q = 0; q < pa.nproj; q++) {
+        uint32_t *dst = pa.dst[q];
+        const int slot = pa.slot[q];
+        if (slot >= 0) {
+            for_slot<KK>(slot, [&](auto C) {
+#pragma unroll
+                for (int r = 0; r < RPT; r++)
+                    if (sel[r]) dst[pos[r]] = v[C][r];
+            });
+        } else {
+            const uint32_t *src = pa.src[q];
+#pragma unroll
+            for (int r = 0; r < RPT; r++)
+                if (sel[r]) dst[pos[r]] = src[row_of(base, r)];
+        }
+    }
+}
+
+// Persistent blocks claim tiles in increasing order from an atomic counter.
+// The next tile is claimed and its loads issued before the current tile is
+// evaluated, so memory stays busy during the look-back wait.
 template <int K, int RPT>
 __global__ __launch_bounds__(kScanBlock) void materialize_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                                  int ntiles, const ProjArgs pa, int32_t *rowids,
@@ -355,86 +237,30 @@ __global__ __launch_bounds__(kScanBlock) void materialize_kernel(const Program P
     constexpr int TILE = kScanBlock * RPT;
     constexpr int NW = kScanBlock / 64;
     constexpr int NJ = RPT / 4;
-    __shared__ int s_tile;
+    constexpr int KK = K > 0 ? K : 1;
+    __shared__ int s_tile[2];
     __shared__ uint32_t s_wcnt[NJ][NW];
     __shared__ unsigned long long s_excl;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    constexpr int KK = K > 0 ? K : 1;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ws->tile_ctr, 1u);
+    uint32_t va[KK][RPT], vb[KK][RPT];
+    if (threadIdx.x == 0) s_tile[0] = (int)atomicAdd(&ws->tile_ctr, 1u);
+    __syncthreads();
+    int t = s_tile[0];
+    if (t < ntiles) load_vals<K, RPT>(cp, (int64_t)t * TILE, n, va);
+    while (t < ntiles) {
+        if (threadIdx.x == 0) s_tile[1] = (int)atomicAdd(&ws->tile_ctr, 1u);
         __syncthreads();
-        const int tile = s_tile;
-        if (tile >= ntiles) break;
-        const int64_t base = (int64_t)tile * TILE;
-        uint32_t v[KK][RPT];
-        uint64_t acc[RPT];
-        load_tile<K, RPT>(cp, base, n, v, acc);
-        run_program<K, RPT>(P, v, acc);
-#pragma unroll
-        for (int j = 0; j < NJ; j++) {
-            const uint32_t c = (uint32_t)(__popcll(acc[4 * j]) + __popcll(acc[4 * j + 1]) +
-                                          __popcll(acc[4 * j + 2]) + __popcll(acc[4 * j + 3]));
-            if (lane == 0) s_wcnt[j][wave] = c;
-        }
+        const int t1 = s_tile[1];
+        if (t1 < ntiles) load_vals<K, RPT>(cp, (int64_t)t1 * TILE, n, vb);
+        compact_tile<K, RPT>(P, va, t, ntiles, n, pa, rowids, cap, ws, status, s_wcnt, &s_excl);
+        if (t1 >= ntiles) break;
+        __syncthreads();   // s_tile, s_wcnt and s_excl are rewritten below
+        if (threadIdx.x == 0) s_tile[0] = (int)atomicAdd(&ws->tile_ctr, 1u);
         __syncthreads();
-        // offset of (chunk j, this wave) inside the tile: chunk-major, then wave
-        uint32_t off[NJ];
-        uint32_t total = 0;
-#pragma unroll
-        for (int j = 0; j < NJ; j++)
-#pragma unroll
-            for (int w = 0; w < NW; w++) {
-                if (w == wave) off[j] = total;
-                total += s_wcnt[j][w];
-            }
-        if (wave == 0) {
-            const unsigned long long ex = lookback(status, tile, total, ws);
-            if (lane == 0) {
-                s_excl = ex;
-                if (tile == ntiles - 1) ws->result = ex + total;
-            }
-        }
+        const int t2 = s_tile[0];
+        if (t2 < ntiles) load_vals<K, RPT>(cp, (int64_t)t2 * TILE, n, va);
+        compact_tile<K, RPT>(P, vb, t1, ntiles, n, pa, rowids, cap, ws, status, s_wcnt, &s_excl);
         __syncthreads();
-        const unsigned long long excl = s_excl;
-        // rank of each selected row of this lane: lanes below first, then e
-        unsigned long long pos[RPT];
-        bool sel[RPT];
-#pragma unroll
-        for (int j = 0; j < NJ; j++) {
-            unsigned long long p = excl + off[j];
-#pragma unroll
-            for (int e = 0; e < 4; e++) p += (unsigned long long)__popcll(acc[4 * j + e] & lt);
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const bool b = (acc[4 * j + e] >> lane) & 1ull;
-                pos[4 * j + e] = p;
-                sel[4 * j + e] = b && p < cap;
-                p += b ? 1 : 0;
-            }
-        }
-        if (rowids) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++)
-                if (sel[r]) rowids[pos[r]] = (int32_t)row_of(base, r);
-        }
-        for (int q = 0; q < pa.nproj; q++) {
-            uint32_t *dst = pa.dst[q];
-            const int slot = pa.slot[q];
-            if (slot >= 0) {
-                for_slot<KK>(slot, [&](auto C) {
-#pragma unroll
-                    for (int r = 0; r < RPT; r++)
-                        if (sel[r]) dst[pos[r]] = v[C][r];
-                });
-            } else {
-                const uint32_t *src = pa.src[q];
-#pragma unroll
-                for (int r = 0; r < RPT; r++)
-                    if (sel[r]) dst[pos[r]] = src[row_of(base, r)];
-            }
-        }
-        __syncthreads();   // s_tile, s_wcnt and s_excl are rewritten next round
+        t = t2;
     }
 }
 

@@ -336,3 +336,143 @@ def device_table(t, device="cuda:0"):
 
 def schema_table(t):
     return Table(t.nrows, t.dtypes, None)
+
+
+class Batch:
+    """Batched COUNT(*) of many predicates over several tables (one hipGraph
+    launch of a persistent kernel)."""
+
+    def __init__(self, ctx: Context, tables, preds, owner, autotune=False, rows_per_thread=0, group=0,
+                 chunk_rows=0, blocks_per_cu=0, stream=None):
+        self.ctx = ctx
+        self.tables = list(tables)
+        self.preds = list(preds)
+        self.owner = np.asarray(owner, np.int32)
+        th = (ctypes.c_void_p * len(self.tables))(*[t.h for t in self.tables])
+        ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
+        o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu)
+        h = ctypes.c_void_p()
+        check(lib().esc_batch_create(ctx.h, th, len(self.tables), ph, self.owner.ctypes.data, len(self.preds),
+                                     ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
+        self.h = h
+
+    def count(self, stream=None):
+        out = np.zeros(len(self.preds), np.uint64)
+        check(lib().esc_batch_count(self.h, _stream_handle(stream), out.ctypes.data))
+        return out
+
+    def update(self, preds, stream=None):
+        self.preds = list(preds)
+        ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
+        check(lib().esc_batch_update(self.h, ph, len(self.preds), _stream_handle(stream)))
+
+    def opts(self):
+        o = BatchOpts()
+        check(lib().esc_batch_get_opts(self.h, ctypes.byref(o)))
+        return {"rows_per_thread": o.rows_per_thread, "group": o.group, "chunk_rows": o.chunk_rows,
+                "blocks_per_cu": o.blocks_per_cu}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_batch_destroy(self.h)
+            self.h = None
+
+
+# ------------------------------------------------------------------ learned gate
+
+def featurize(schema: Table, preds, cmin, cmax):
+    """64 float32 features per compiled predicate (host, in the library)."""
+    vmin = (Value * len(schema.dtypes))()
+    vmax = (Value * len(schema.dtypes))()
+    for c, dt in enumerate(schema.dtypes):
+        for arr, v in ((vmin, cmin[c]), (vmax, cmax[c])):
+            if dt == FLOAT32:
+                arr[c].f = float(np.float32(v))
+            else:
+                arr[c].i = int(v)
+    ph = (ctypes.c_void_p * max(len(preds), 1))(*[p.h for p in preds])
+    out = np.zeros((len(preds), 64), np.float32)
+    check(lib().esc_featurize(schema.h, vmin, vmax, ph, len(preds), out.ctypes.data))
+    return out
+
+
+def params_to_flat(params):
+    parts = []
+    for w, b in params:
+        parts.append(np.asarray(w, np.float32).reshape(-1))
+        parts.append(np.asarray(b, np.float32).reshape(-1))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == MLP_NPARAMS
+    return flat
+
+
+def flat_to_params(flat, dims=(64, 256, 256, 256, 1)):
+    out, o = [], 0
+    for i in range(len(dims) - 1):
+        w = flat[o:o + dims[i] * dims[i + 1]].reshape(dims[i], dims[i + 1]); o += w.size
+        b = flat[o:o + dims[i + 1]]; o += b.size
+        out.append((w, b))
+    return out
+
+
+class MLP:
+    """The estimator on the device (weights, Adam state and work buffers)."""
+
+    def __init__(self, ctx: Context, params=None):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        check(lib().esc_mlp_create(ctx.h, ctypes.byref(h)))
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        flat = params if isinstance(params, np.ndarray) else params_to_flat(params)
+        flat = np.ascontiguousarray(flat, np.float32)
+        check(lib().esc_mlp_set_params(self.h, flat.ctypes.data))
+
+    def get_params(self):
+        flat = np.zeros(MLP_NPARAMS, np.float32)
+        check(lib().esc_mlp_get_params(self.h, flat.ctypes.data))
+        return flat
+
+    def predict(self, x, out=None, stream=None):
+        import torch
+        n = x.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device=x.device) if out is None else out
+        check(lib().esc_mlp_predict(self.h, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream)))
+        return out
+
+    def gradients(self, x, y, stream=None):
+        import torch
+        g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+        check(lib().esc_mlp_gradients(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                      x.shape[0], ctypes.c_void_p(g.data_ptr()), _stream_handle(stream)))
+        return g
+
+    def train(self, x, y, order, steps, batch, lr=1e-3, stream=None, want_loss=True):
+        loss = np.zeros(max(steps, 1), np.float32)
+        check(lib().esc_mlp_train(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                  ctypes.c_void_p(order.data_ptr()), steps, batch, float(lr),
+                                  _stream_handle(stream), loss.ctypes.data if want_loss else None))
+        return loss[:steps]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_mlp_destroy(self.h)
+            self.h = None
+
+
+def gate_pushdown(yhat, nrows, tau, beta, min_rows):
+    y = np.ascontiguousarray(yhat, np.float32)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(nrows, np.int64), y.shape))
+    r = np.zeros(len(y), np.uint8)
+    check(lib().esc_gate_pushdown(y.ctypes.data, n.ctypes.data, len(y), tau, beta, int(min_rows), r.ctypes.data))
+    return r.astype(bool)
+
+
+def gate_join_pair(yr, nr, ys, ns, beta):
+    r = ctypes.c_uint8()
+    check(lib().esc_gate_join_pair(float(yr), int(nr), float(ys), int(ns), float(beta), ctypes.byref(r)))
+    return bool(r.value)

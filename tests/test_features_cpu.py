@@ -1,0 +1,50 @@
+"""The library's featurization and gate (host code) against their CPU
+oracle: features must match bit for bit, routing decisions exactly."""
+import math
+
+import numpy as np
+
+from oracle import features as fo
+from paper_1901_01488_amd import datagen as dg
+from paper_1901_01488_amd import esc
+
+
+def test_featurize_matches_oracle_bitwise():
+    t = dg.table_mixed(50_000, 6, seed=3, kinds=dg.LEARNED_KINDS)
+    cmin = [c.min() for c in t.cols]
+    cmax = [c.max() for c in t.cols]
+    schema = esc.schema_table(t)
+    preds = dg.preds_mixed(t, 300, seed=4)
+    cps = [esc.Pred(schema, p) for p in preds]
+    got = esc.featurize(schema, cps, cmin, cmax)
+    want = fo.featurize_many(preds, cmin, cmax)
+    assert got.shape == want.shape == (300, 64)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_featurize_golden_cases_through_library():
+    from test_oracle_mlp import _read_feature_golden
+    schema = esc.Table(10, [dg.INT32, dg.INT32, dg.INT32, dg.INT32, dg.INT32, dg.FLOAT32])
+    cmin = [0, 0, 0, 0, 0, np.float32(1.0)]
+    cmax = [100, 9, 1000, 1, 0, np.float32(3.0)]
+    for case in _read_feature_golden():
+        got = esc.featurize(schema, [esc.Pred(schema, case["pred"])], cmin, cmax)[0]
+        want = fo.featurize(case["pred"], cmin, cmax)
+        assert np.array_equal(got, want), case["pred"]
+
+
+def test_gate_matches_oracle():
+    rng = np.random.default_rng(5)
+    n = np.array([10**5, 10**6, 10**7, 10**8, 10**9])
+    for tau, beta in [(0.05, 1.25), (0.05, 2.0), (0.2, 1.5), (1.0, 1.0)]:
+        y = rng.uniform(-22, 1, 2000).astype(np.float32)
+        nr = rng.choice(n, 2000)
+        got = esc.gate_pushdown(y, nr, tau, beta, 10**6)
+        want = np.array([fo.route_pushdown(float(a), int(b), tau, beta, 10**6) for a, b in zip(y, nr)])
+        assert np.array_equal(got, want)
+    for _ in range(500):
+        yr, ys = (float(np.float32(v)) for v in rng.uniform(-15, 0, 2))
+        nr, ns = (int(v) for v in rng.choice(n, 2))
+        assert esc.gate_join_pair(yr, nr, ys, ns, 1.5) == fo.route_join_pair(yr, nr, ys, ns, 1.5)
+    # a prediction exactly at tau is routed
+    assert esc.gate_pushdown(np.array([math.log(0.05)], np.float32), 10**8, 0.05, 1.25, 10**6)[0]
