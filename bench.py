@@ -163,10 +163,13 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras.update(plain_latency(ctx, esc, dg, torch, dev))
-        del dt, t, rowids, outs
-        torch.cuda.empty_cache()
-        extras.update(batched_vs_plain(ctx, esc, dg, torch, dev))
+        for name, fn in (("plain_latency", lambda: plain_latency(ctx, esc, dg, torch, dev)),
+                         ("batched", lambda: batched_vs_plain(ctx, esc, dg, torch, dev))):
+            try:
+                extras.update(fn())
+            except Exception as e:   # an extra must not hide the headline line; the error is reported
+                extras[name + "_error"] = repr(e)[:300]
+            torch.cuda.empty_cache()
 
     line = {
         "metric": "ESC scan GB/s vs HBM peak; predicates/s batched vs plain; p50/p99 ms/query",

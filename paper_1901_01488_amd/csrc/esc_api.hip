@@ -5,9 +5,11 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
+#include <utility>
 
 #include "esc_host.h"
 #include "esc_kernels.h"
@@ -48,14 +50,67 @@ int check_scan_args(const esc_ctx *ctx, const esc_table *t, const esc_pred *p, c
     return ESC_OK;
 }
 
-ColPtrs slot_ptrs(const esc_table *t, const Program &P)
+ColPtrs slot_ptrs(const esc_table *t, const Program &P, int nt)
 {
     ColPtrs cp{};
+    cp.nt = nt;
     for (int s = 0; s < P.nslots; s++) cp.p[s] = (const uint32_t *)t->cols[P.slot_col[s]];
     return cp;
 }
 
 __global__ void store_u64_kernel(unsigned long long *dst, unsigned long long v) { *dst = v; }
+
+// Workspace of a materialization: header, per-wave-tile counts (uint32),
+// then row-order offsets (uint32, one more than there are tiles).
+struct WsLayout {
+    int64_t ntiles;
+    size_t counts_off, offsets_off, bytes;
+};
+
+WsLayout ws_layout(int64_t nrows, int rpt)
+{
+    WsLayout L;
+    const int64_t tile = 64 * (int64_t)rpt;
+    L.ntiles = (nrows + tile - 1) / tile;
+    L.counts_off = sizeof(WsHeader);
+    L.offsets_off = (L.counts_off + (size_t)L.ntiles * 4 + 255) & ~(size_t)255;
+    L.bytes = L.offsets_off + (size_t)(L.ntiles + 1) * 4;
+    return L;
+}
+
+// Which (table, predicate, tile size) the per-tile counts in a workspace
+// belong to; kept per context, keyed by the workspace address.
+struct TileRecord {
+    uint64_t table_id, pred_id;
+    int64_t nrows;
+    int rpt;
+};
+
+static std::mutex g_rec_mu;
+static std::map<std::pair<const esc_ctx *, const void *>, TileRecord> g_records;
+
+void remember_tiles(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt)
+{
+    std::lock_guard<std::mutex> g(g_rec_mu);
+    g_records[{ctx, ws}] = TileRecord{t->id, p->id, t->nrows, rpt};
+}
+
+bool tiles_valid(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt)
+{
+    std::lock_guard<std::mutex> g(g_rec_mu);
+    auto it = g_records.find({ctx, ws});
+    return it != g_records.end() && it->second.table_id == t->id && it->second.pred_id == p->id &&
+           it->second.nrows == t->nrows && it->second.rpt == rpt;
+}
+
+void forget_tiles(const esc_ctx *ctx, const void *ws)
+{
+    std::lock_guard<std::mutex> g(g_rec_mu);
+    if (ws) g_records.erase({ctx, ws});
+    else
+        for (auto it = g_records.begin(); it != g_records.end();)
+            it = it->first.first == ctx ? g_records.erase(it) : std::next(it);
+}
 
 }  // namespace esc
 
@@ -81,10 +136,16 @@ int esc_ctx_create(int device, esc_ctx **out)
         delete c;
         return hip_fail(e, "hipHostMalloc");
     }
-    const char *r = getenv("ESC_COUNT_RPT");
-    if (r && (atoi(r) == 4 || atoi(r) == 8)) c->rpt_count = atoi(r);
+    const char *r = getenv("ESC_COUNT_VARIANT");
+    if (r && atoi(r) >= 0 && atoi(r) <= 4) c->count_variant = atoi(r);
+    r = getenv("ESC_NONTEMPORAL");
+    if (r) c->nt = atoi(r) != 0;
+    r = getenv("ESC_BLOCKS_PER_CU");
+    if (r) c->bpc = atoi(r);
+    r = getenv("ESC_MAT_BLOCKS_PER_CU");
+    if (r) c->mat_bpc = atoi(r);
     r = getenv("ESC_MAT_RPT");
-    if (r && (atoi(r) == 4 || atoi(r) == 8)) c->rpt_mat = atoi(r);
+    if (r && (atoi(r) == 8 || atoi(r) == 16)) c->rpt_mat = atoi(r);
     *out = c;
     return ESC_OK;
 }
@@ -92,6 +153,7 @@ int esc_ctx_create(int device, esc_ctx **out)
 int esc_ctx_destroy(esc_ctx *ctx)
 {
     if (!ctx) return ESC_OK;
+    forget_tiles(ctx, nullptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return ESC_OK;
@@ -108,11 +170,7 @@ int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
 {
     if (!t || !bytes) return fail(ESC_ERR_INVALID, "null argument");
     size_t need = sizeof(WsHeader);
-    if (materialize) {
-        // tiles of the smallest variant (RPT = 4)
-        const int64_t tile = (int64_t)kScanBlock * 4;
-        need += (size_t)((t->nrows + tile - 1) / tile) * 8;
-    }
+    if (materialize) need = ws_layout(t->nrows, 8).bytes;   // the smallest wave tile needs the most slots
     *bytes = (need + 255) & ~(size_t)255;
     return ESC_OK;
 }
@@ -121,13 +179,16 @@ int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream
 {
     if (!ctx || !dev_ws || ws_bytes < sizeof(WsHeader)) return fail(ESC_ERR_INVALID, "bad workspace");
     (void)hipSetDevice(ctx->device);
+    forget_tiles(ctx, dev_ws);
     launch_zero((unsigned long long *)dev_ws, (int64_t)(ws_bytes / 8), (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ESC_OK : hip_fail(e, "zero kernel launch");
 }
 
+// Launches the count kernel; stores per-wave-tile counts in the workspace
+// when it has room for them (and remembers for which table and predicate).
 static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
-                        hipStream_t s, unsigned long long *dev_out)
+                        hipStream_t s, unsigned long long *dev_out, bool need_tiles)
 {
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
     if (rc) return rc;
@@ -137,14 +198,19 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
         const unsigned long long v = (P.flags & P_ALWAYS_TRUE) ? (unsigned long long)t->nrows : 0ull;
         hipLaunchKernelGGL(store_u64_kernel, dim3(1), dim3(1), 0, s, dev_out, v);
     } else {
-        const int rpt = ctx->rpt_count;
-        CountFn fn = count_fn(P.nslots, rpt);
-        const int64_t tile = (int64_t)kScanBlock * rpt;
-        const int64_t ntiles = (t->nrows + tile - 1) / tile;
-        int64_t grid = (int64_t)ctx->num_cus * occupancy((const void *)fn, kScanBlock, 0);
-        if (grid > ntiles) grid = ntiles;
-        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P), t->nrows,
-                           (WsHeader *)dev_ws, dev_out);
+        const int rpt = count_rpt(ctx->count_variant);
+        const WsLayout L = ws_layout(t->nrows, rpt);
+        uint32_t *tiles = nullptr;
+        if (ws_bytes >= L.bytes) tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
+        else if (need_tiles) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, L.bytes);
+        CountFn fn = count_fn(P.nslots, ctx->count_variant);
+        const int occ = occupancy((const void *)fn, kScanBlock, 0);
+        int64_t grid = (int64_t)ctx->num_cus * (ctx->bpc > 0 ? ctx->bpc : occ);
+        const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
+        if (grid > blocks_needed) grid = blocks_needed;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
+                           (WsHeader *)dev_ws, dev_out, tiles);
+        if (tiles) remember_tiles(ctx, dev_ws, t, p, rpt);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ESC_OK : hip_fail(e, "count kernel launch");
@@ -156,7 +222,7 @@ int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws,
     if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
     hipStream_t s = (hipStream_t)stream;
     WsHeader *h = (WsHeader *)dev_ws;
-    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, h ? &h->result : nullptr);
+    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, h ? &h->result : nullptr, false);
     if (rc) return rc;
     hipError_t e = hipMemcpyAsync(ctx->pinned, &h->result, 8, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
@@ -169,7 +235,7 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *d
                     void *stream, uint64_t *dev_count)
 {
     if (!dev_count) return fail(ESC_ERR_INVALID, "null dev_count");
-    return count_launch(ctx, t, p, dev_ws, ws_bytes, (hipStream_t)stream, (unsigned long long *)dev_count);
+    return count_launch(ctx, t, p, dev_ws, ws_bytes, (hipStream_t)stream, (unsigned long long *)dev_count, false);
 }
 
 int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols, int nproj,
@@ -177,10 +243,11 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
                     size_t ws_bytes, void *stream, uint64_t *out_count)
 {
     if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
-    size_t need = 0;
-    int rc = t ? esc_workspace_size(t, 1, &need) : fail(ESC_ERR_INVALID, "null table");
+    if (!ctx || !t) return fail(ESC_ERR_INVALID, "null handle");
+    const int rpt = count_rpt(ctx->count_variant);
+    const WsLayout L = ws_layout(t->nrows, rpt);
+    int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, L.bytes);
     if (rc) return rc;
-    if ((rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, need))) return rc;
     if (nproj < 0 || nproj > ESC_MAX_PROJ) return fail(ESC_ERR_INVALID, "nproj %d outside [0, %d]", nproj, ESC_MAX_PROJ);
     if (nproj > 0 && !proj_cols) return fail(ESC_ERR_INVALID, "null proj_cols");
     if (capacity > 0 && nproj > 0 && !dev_proj_out) return fail(ESC_ERR_INVALID, "null projection outputs");
@@ -204,27 +271,34 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     }
     (void)hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
-    const int rpt = ctx->rpt_mat;
-    const int64_t tile = (int64_t)kScanBlock * rpt;
-    const int ntiles = (int)((t->nrows + tile - 1) / tile);
     WsHeader *h = (WsHeader *)dev_ws;
-    unsigned long long *status = (unsigned long long *)(h + 1);
-    launch_zero((unsigned long long *)dev_ws, (int64_t)(sizeof(WsHeader) / 8) + ntiles, s);
-    MatFn fn = mat_fn(P.nslots, rpt);
-    int64_t grid = (int64_t)ctx->num_cus * occupancy((const void *)fn, kScanBlock, 0);
-    if (grid > ntiles) grid = ntiles;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P), t->nrows, ntiles, pa,
-                       capacity > 0 ? dev_rowids : nullptr, (unsigned long long)capacity, h, status);
+    uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
+    uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
+    // pass 1: per-wave-tile counts, unless the preceding count left them
+    if (!tiles_valid(ctx, dev_ws, t, p, rpt)) {
+        if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true))) return rc;
+    }
+    // pass 2: offsets in row order
+    launch_scan(tiles, L.ntiles, offsets, h, s);
+    // pass 3: write
+    if (capacity > 0) {
+        WriteFn fn = write_fn(P.nslots, rpt);
+        const int occ = occupancy((const void *)fn, kScanBlock, 0);
+        int64_t grid = (int64_t)ctx->num_cus * (ctx->mat_bpc > 0 ? std::min(ctx->mat_bpc, occ) : occ);
+        const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
+        if (grid > blocks_needed) grid = blocks_needed;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
+                           offsets, pa, dev_rowids, (unsigned long long)capacity);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "materialize kernel launch");
-    if ((e = hipMemcpyAsync(ctx->pinned, h, sizeof(WsHeader), hipMemcpyDeviceToHost, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ctx->pinned, &h->result, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    const WsHeader *hh = (const WsHeader *)ctx->pinned;
-    if (hh->error) return fail(ESC_ERR_TIMEOUT, "look-back wait expired; results undefined");
-    *out_count = hh->result;
-    if (hh->result > capacity) return fail(ESC_ERR_CAPACITY, "%llu rows qualify, capacity %llu", hh->result,
-                                           (unsigned long long)capacity);
+    const unsigned long long total = ctx->pinned[0];
+    *out_count = total;
+    if (total > capacity)
+        return fail(ESC_ERR_CAPACITY, "%llu rows qualify, capacity %llu", total, (unsigned long long)capacity);
     return ESC_OK;
 }
 

@@ -54,31 +54,27 @@ struct BatchItem {
     int32_t pad;
 };
 
+// The waves of a block walk the item's wave tiles independently; each wave
+// tile is loaded once and every predicate of the group runs on it.
 template <int K, int RPT>
 __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
                                          uint32_t (*s_cnt)[kScanBlock / 64])
 {
-    constexpr int TILE = kScanBlock * RPT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int TILE = kWave * RPT;
+    constexpr int NW = kScanBlock / kWave;
+    const int wave = threadIdx.x >> 6;
     ColPtrs cp{};
+    cp.nt = 1;
 #pragma unroll
     for (int c = 0; c < K; c++) cp.p[c] = g.cols[c];
     const int npred = g.npred;
-    for (int64_t base = it.r0; base < it.r1; base += TILE) {
+    for (int64_t base = it.r0 + (int64_t)wave * TILE; base < it.r1; base += (int64_t)NW * TILE) {
         uint32_t v[K][RPT];
         load_vals<K, RPT>(cp, base, it.r1, v);
-        const bool full = base + TILE <= it.r1;
+        const uint32_t valid = valid_bits<RPT>(base, it.r1);
         for (int i = 0; i < npred; i++) {
-            uint64_t acc[RPT];
-            // the valid-row masks are rebuilt per predicate (cheap) rather than
-            // kept live across the program, to spare scalar registers
-#pragma unroll
-            for (int r = 0; r < RPT; r++) acc[r] = full ? ~0ull : __ballot(row_of(base, r) < it.r1);
-            run_program<K, RPT>(progs[g.pbegin + i], v, acc);
-            uint32_t c = 0;
-#pragma unroll
-            for (int r = 0; r < RPT; r++) c += (uint32_t)__popcll(acc[r]);
-            if (lane == 0) s_cnt[i][wave] += c;
+            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT>(progs[g.pbegin + i], v, valid)));
+            if (lane_id() == 0) s_cnt[i][wave] += c;
         }
     }
 }
@@ -128,7 +124,7 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
 typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, int, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
-static BatchFn batch_fn(int rpt) { return rpt == 4 ? batch_kernel<4> : batch_kernel<8>; }
+static BatchFn batch_fn(int rpt) { return rpt == 16 ? batch_kernel<16> : batch_kernel<8>; }
 
 __global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
 {
@@ -401,7 +397,7 @@ int autotune(esc_batch *b, hipStream_t s)
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ESC_ERR_HIP, "hipEventCreate failed");
     int rc = ESC_OK;
-    const int rpts[] = {8, 4};
+    const int rpts[] = {16, 8};
     const int groups[] = {0, 16, 8};
     const int chunks[] = {1 << 17, 1 << 19, 1 << 21};
     for (int rpt : rpts)
@@ -504,7 +500,7 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     }
     esc_batch_opts o{};
     if (opts) o = *opts;
-    if (o.rows_per_thread != 4) o.rows_per_thread = 8;
+    if (o.rows_per_thread != 16) o.rows_per_thread = 8;
     o.block = kScanBlock;
     if (opts && opts->autotune) rc = autotune(b, (hipStream_t)stream);
     else rc = install(b, o);

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <set>
 #include <vector>
@@ -37,6 +38,12 @@ int fail(int status, const char *fmt, ...)
 }
 
 void clear_error() { g_err[0] = 0; }
+
+uint64_t next_handle_id()
+{
+    static std::atomic<uint64_t> next{1};
+    return next.fetch_add(1);
+}
 
 const char *last_error() { return g_err; }
 
@@ -448,6 +455,7 @@ int esc_table_create(int64_t nrows, int ncols, const int32_t *dtypes, const void
         }
     esc_table *t = new (std::nothrow) esc_table;
     if (!t) return fail(ESC_ERR_OOM, "out of host memory");
+    t->id = esc::next_handle_id();
     t->nrows = nrows;
     t->dtypes.assign(dtypes, dtypes + ncols);
     if (dev_cols) t->cols.assign(dev_cols, dev_cols + ncols);
@@ -469,6 +477,7 @@ int esc_compile_predicate(const esc_table *schema, const esc_node *nodes, int nn
     if (!p) return esc::fail(ESC_ERR_OOM, "out of host memory");
     int rc = esc::compile(schema, nodes, nnodes, consts, nconsts, udf, nudf, p);
     if (rc) { delete p; return rc; }
+    p->id = esc::next_handle_id();
     p->ncols_schema = (int)schema->dtypes.size();
     p->schema_dtypes = schema->dtypes;
     p->nodes.assign(nodes, nodes + nnodes);

@@ -1,9 +1,16 @@
 // esc_device.h -- device-side evaluation of a compiled predicate program on
 // a tile of rows held in registers (shared by the plain and batched scans).
 //
-// Tile layout: a block of kScanBlock threads covers kScanBlock*RPT rows; row
-// slot r = 4*j + e of thread t is row base + (j*kScanBlock + t)*4 + e, so the
-// j-th 16-byte load of every lane of a wave forms one coalesced 1 KiB request.
+// Tile layout: each wave owns a contiguous "wave tile" of 64*RPT rows; row
+// slot r = 4*j + e of lane l is row base + j*256 + l*4 + e, so the j-th
+// 16-byte load of the 64 lanes is one coalesced 1 KiB request, and the rows
+// of a wave tile in row order are (j, lane, e).  Waves never wait for each
+// other: a scan is a grid-stride loop over wave tiles.
+//
+// Truth values are per-lane bit masks: bit r of a lane's mask is the value
+// for its row slot r.  A test costs three vector ops per row slot (compare
+// and shift-in), clause logic costs one op per test for all RPT rows, and
+// the scalar unit is left to the wave-uniform interpretation of the program.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,71 +35,61 @@ __device__ __forceinline__ void for_slot(int s, F &&f)
     }
 }
 
-// Lane masks of one test, folded straight into the clause state: MODE 0 ORs
-// into the open clause cm, MODE 1 (a one-leaf clause) ANDs into acc.
-template <int MODE, int RPT, typename T>
-__device__ __forceinline__ void fold(uint64_t (&acc)[RPT], uint64_t (&cm)[RPT], T &&test)
+// Per-lane mask of a row test: bit r = test(r).
+template <int RPT, typename T>
+__device__ __forceinline__ uint32_t bits_of(T &&test)
 {
+    static_assert(RPT <= 32, "masks are 32-bit");
+    uint32_t m = 0;
 #pragma unroll
-    for (int r = 0; r < RPT; r++) {
-        const uint64_t m = __ballot(test(r));
-        if (MODE == 0) cm[r] |= m;
-        else acc[r] &= m;
-    }
+    for (int r = RPT - 1; r >= 0; r--) m = m + m + (test(r) ? 1u : 0u);
+    return m;
 }
 
-template <int MODE, int RPT>
-__device__ __forceinline__ void run_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT],
-                                         uint64_t (&acc)[RPT], uint64_t (&cm)[RPT])
+template <int RPT>
+__device__ __forceinline__ uint32_t all_rows()
+{
+    return RPT == 32 ? 0xffffffffu : ((1u << RPT) - 1u);
+}
+
+template <int RPT>
+__device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT])
 {
     switch (I.op) {
     case T_RANGE_I32: {
         const uint32_t lo = (uint32_t)I.a, span = (uint32_t)I.b;
-        fold<MODE>(acc, cm, [&](int r) { return x[r] - lo <= span; });
-        break;
+        return bits_of<RPT>([&](int r) { return x[r] - lo <= span; });
     }
     case T_RANGE_F32: {
         const float lo = as_f((uint32_t)I.a), hi = as_f((uint32_t)I.b);
-        fold<MODE>(acc, cm, [&](int r) { const float f = as_f(x[r]); return lo <= f && f <= hi; });
-        break;
+        return bits_of<RPT>([&](int r) { const float f = as_f(x[r]); return lo <= f && f <= hi; });
     }
     case T_BITSET: {
         const uint32_t lo = (uint32_t)I.a;
         const uint64_t bits = (uint64_t)(uint32_t)I.b | ((uint64_t)(uint32_t)I.c << 32);
-        fold<MODE>(acc, cm, [&](int r) {
+        return bits_of<RPT>([&](int r) {
             const uint32_t d = x[r] - lo;
             return d < 64u && ((bits >> (d & 63u)) & 1ull);
         });
-        break;
     }
-    case T_IN_I32:
-    case T_IN_F32: {
-        // OR over the set members into cm; a one-leaf clause (MODE 1) finds
-        // cm empty on entry, uses it as scratch and leaves it empty
-        const bool fl = I.op == T_IN_F32;
+    case T_IN_I32: {
+        uint32_t m = 0;
         for (int k = 0; k < I.b; k++) {
             const uint32_t kv = kpool[I.a + k];
-            if (fl) {
-                const float kf = as_f(kv);
-#pragma unroll
-                for (int r = 0; r < RPT; r++) cm[r] |= __ballot(as_f(x[r]) == kf);
-            } else {
-#pragma unroll
-                for (int r = 0; r < RPT; r++) cm[r] |= __ballot(x[r] == kv);
-            }
+            m |= bits_of<RPT>([&](int r) { return x[r] == kv; });
         }
-        if (MODE == 1) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) { acc[r] &= cm[r]; cm[r] = 0; }
-        }
-        break;
+        return m;
     }
-    default:
-        if (MODE == 1) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) acc[r] = 0;
+    case T_IN_F32: {
+        uint32_t m = 0;
+        for (int k = 0; k < I.b; k++) {
+            const float kf = as_f(kpool[I.a + k]);
+            m |= bits_of<RPT>([&](int r) { return as_f(x[r]) == kf; });
         }
+        return m;
     }
+    }
+    return 0u;
 }
 
 template <int K, int RPT, int KK = (K > 0 ? K : 1)>
@@ -154,15 +151,14 @@ __device__ __forceinline__ void run_udf(const Insn &I, const uint32_t (&v)[KK][R
     }
 }
 
-// Runs the program on the loaded slots; acc[r] enters as the mask of valid
-// rows and leaves as the mask of qualifying rows.
+// Runs the program on the loaded slots: returns valid & P(row) per row slot.
 template <int K, int RPT, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ void run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint64_t (&acc)[RPT])
+__device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid)
 {
-    uint64_t cm[RPT];
+    uint32_t acc = valid, cm = 0;
     uint32_t u[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; r++) { cm[r] = 0; u[r] = 0; }
+    for (int r = 0; r < RPT; r++) u[r] = 0;
     const int n = P.ninsn;
     for (int i = 0; i < n; i++) {
         const Insn I = P.insn[i];
@@ -170,41 +166,43 @@ __device__ __forceinline__ void run_program(const Program &P, const uint32_t (&v
             run_udf<K, RPT>(I, v, u);
             continue;
         }
-        const bool single = I.flags & F_SINGLE;
-        if (I.flags & F_SRC_UDF) {
-            if (single) run_test<1, RPT>(I, P.kpool, u, acc, cm);
-            else run_test<0, RPT>(I, P.kpool, u, acc, cm);
-        } else if (single) {
-            for_slot<K>(I.src, [&](auto C) { run_test<1, RPT>(I, P.kpool, v[C], acc, cm); });
+        uint32_t m = 0;
+        if (I.flags & F_SRC_UDF) m = run_test<RPT>(I, P.kpool, u);
+        else for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+        if (I.flags & F_SINGLE) {
+            acc &= m;
         } else {
-            for_slot<K>(I.src, [&](auto C) { run_test<0, RPT>(I, P.kpool, v[C], acc, cm); });
-        }
-        if (!single && (I.flags & F_END_CLAUSE)) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) { acc[r] &= cm[r]; cm[r] = 0; }
+            cm |= m;
+            if (I.flags & F_END_CLAUSE) { acc &= cm; cm = 0; }
         }
     }
+    return acc;
 }
 
-// Row of slot r for this thread: base + (j*256 + tid)*4 + e with r = 4j + e.
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Row of slot r of this lane in the wave tile starting at `base`.
 __device__ __forceinline__ int64_t row_of(int64_t base, int r)
 {
-    return base + ((int64_t)(r >> 2) * kScanBlock + threadIdx.x) * 4 + (r & 3);
+    return base + (int64_t)(r >> 2) * (4 * kWave) + lane_id() * 4 + (r & 3);
 }
 
-// Loads the K slot columns of the tile starting at row `base`; rows at or
-// beyond n (only in the last tile) read as 0 and are masked by valid_masks.
+// Loads the K slot columns of the wave tile starting at row `base`; rows at
+// or beyond n (only in the last tile) read as 0 and are masked by valid_bits.
 template <int K, int RPT, int KK = (K > 0 ? K : 1)>
 __device__ __forceinline__ void load_vals(const ColPtrs &cp, int64_t base, int64_t n, uint32_t (&v)[KK][RPT])
 {
-    constexpr int TILE = kScanBlock * RPT;
+    constexpr int TILE = kWave * RPT;
     if (base + TILE <= n) {
 #pragma unroll
         for (int j = 0; j < RPT / 4; j++) {
-            const int64_t idx = base + ((int64_t)j * kScanBlock + threadIdx.x) * 4;
+            const int64_t idx = base + (int64_t)j * (4 * kWave) + lane_id() * 4;
 #pragma unroll
             for (int c = 0; c < K; c++) {
-                const u32x4 q = __builtin_nontemporal_load((const u32x4 *)(cp.p[c] + idx));
+                const u32x4 *src = (const u32x4 *)(cp.p[c] + idx);
+                const u32x4 q = cp.nt ? __builtin_nontemporal_load(src) : *src;
                 v[c][4 * j + 0] = q.x;
                 v[c][4 * j + 1] = q.y;
                 v[c][4 * j + 2] = q.z;
@@ -222,28 +220,29 @@ __device__ __forceinline__ void load_vals(const ColPtrs &cp, int64_t base, int64
     }
 }
 
-// Lane masks of the rows of the tile that exist (all ones except in the last tile).
+// Bits of the row slots of this lane that exist (all but in the last tile).
 template <int RPT>
-__device__ __forceinline__ void valid_masks(int64_t base, int64_t n, uint64_t (&acc)[RPT])
+__device__ __forceinline__ uint32_t valid_bits(int64_t base, int64_t n)
 {
-    constexpr int TILE = kScanBlock * RPT;
-    const bool full = base + TILE <= n;
-#pragma unroll
-    for (int r = 0; r < RPT; r++) acc[r] = full ? ~0ull : __ballot(row_of(base, r) < n);
+    constexpr int TILE = kWave * RPT;
+    if (base + TILE <= n) return all_rows<RPT>();
+    return bits_of<RPT>([&](int r) { return row_of(base, r) < n; });
 }
 
-// Qualifying rows of a loaded tile, as the count of set lane-mask bits.
+// Qualifying rows of a loaded tile for this lane.
 template <int K, int RPT, int KK = (K > 0 ? K : 1)>
 __device__ __forceinline__ uint32_t eval_count(const Program &P, const uint32_t (&v)[KK][RPT], int64_t base,
                                                int64_t n)
 {
-    uint64_t acc[RPT];
-    valid_masks<RPT>(base, n, acc);
-    run_program<K, RPT>(P, v, acc);
-    uint32_t c = 0;
+    return (uint32_t)__popc(run_program<K, RPT>(P, v, valid_bits<RPT>(base, n)));
+}
+
+// Sum of a per-lane value over the wave.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x)
+{
 #pragma unroll
-    for (int r = 0; r < RPT; r++) c += (uint32_t)__popcll(acc[r]);
-    return c;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
 }
 
 }  // namespace esc

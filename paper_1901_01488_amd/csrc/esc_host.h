@@ -9,6 +9,7 @@
 #include "esc_program.h"
 
 struct esc_table {
+    uint64_t id = 0;   // unique per table handle (never reused)
     int64_t nrows = 0;
     std::vector<int32_t> dtypes;
     std::vector<const void *> cols;   // empty for a schema-only table
@@ -16,6 +17,7 @@ struct esc_table {
 };
 
 struct esc_pred {
+    uint64_t id = 0;   // unique per predicate handle (never reused)
     esc::Program prog{};
     int ncols_schema = 0;
     std::vector<int32_t> schema_dtypes;
@@ -30,6 +32,7 @@ namespace esc {
 
 // thread-local error message; returns `status` so callers can `return fail(...)`
 int fail(int status, const char *fmt, ...);
+uint64_t next_handle_id();
 void clear_error();
 
 // host compiler (no HIP): fills p->prog from the tree

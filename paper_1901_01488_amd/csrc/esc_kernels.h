@@ -13,6 +13,7 @@ constexpr int kScanBlock = 256;
 // device pointers of the loaded column slots
 struct ColPtrs {
     const uint32_t *p[kMaxSlots];
+    int32_t nt;   // 1: streaming (non-temporal) loads
 };
 
 // projected columns of a materialization: slot >= 0 when the column is
@@ -24,24 +25,24 @@ struct ProjArgs {
     uint32_t *dst[ESC_MAX_PROJ];
 };
 
-// first 64 bytes of a scan workspace; tile status words follow
+// first 64 bytes of a scan workspace; per-wave-tile counts and output offsets follow
 struct WsHeader {
     unsigned long long total;    // count: running sum (reset by the last block)
     unsigned int ticket;         // count: blocks done (reset by the last block)
-    unsigned int error;          // materialize: a bounded wait expired
-    unsigned long long result;   // the count of the last call
-    unsigned int tile_ctr;       // materialize: next tile to claim
     unsigned int pad0;
-    unsigned long long pad1[4];
+    unsigned long long result;   // the count of the last call
+    unsigned long long pad1[5];
 };
 static_assert(sizeof(WsHeader) == 64, "workspace header is 64 bytes");
 
-typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsigned long long *);
-typedef void (*MatFn)(const Program, const ColPtrs, int64_t, int, const ProjArgs, int32_t *, unsigned long long,
-                      WsHeader *, unsigned long long *);
+typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsigned long long *, uint32_t *);
+typedef void (*WriteFn)(const Program, const ColPtrs, int64_t, const uint32_t *, const ProjArgs, int32_t *,
+                        unsigned long long);
 
-CountFn count_fn(int nslots, int rpt);
-MatFn mat_fn(int nslots, int rpt);
+CountFn count_fn(int nslots, int variant);
+int count_rpt(int variant);
+WriteFn write_fn(int nslots, int rpt);
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s);
+void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s);
 
 }  // namespace esc

@@ -216,12 +216,18 @@ def table_mixed(n, ncols, seed, device=None, kinds=None) -> Table:
     if kinds is None:
         pool = ["uniform", "zipf", "correlated", "uniform6", "lognormal"]
         kinds = ["perm"] + [pool[int(pick.integers(0, len(pool)))] for _ in range(ncols - 1)]
-        if "uniform" not in kinds[1:] and "correlated" in kinds:
-            kinds[kinds.index("correlated")] = "uniform"
+        if "correlated" in kinds:
+            # a correlated column derives from an earlier uniform column
+            first_c = kinds.index("correlated")
+            if "uniform" not in kinds:
+                kinds[first_c] = "uniform"
+            elif kinds.index("uniform") > first_c:
+                u = kinds.index("uniform")
+                kinds[first_c], kinds[u] = "uniform", "correlated"
     cols, dtypes, domain = [], [], []
     for j, kd in enumerate(kinds):
         if kd == "perm":
-            cols.append(b.perm(n)); dtypes.append(INT32); domain.append((0, n - 1))
+            cols.append(b.perm(n)); dtypes.append(INT32); domain.append((0, max(n - 1, 0)))
         elif kd == "uniform":
             cols.append(b.uniform(0, 10_000, n)); dtypes.append(INT32); domain.append((0, 9_999))
         elif kd == "uniform6":

@@ -1,0 +1,157 @@
+"""Planning-time workload: arriving three-table join queries whose selection
+cardinalities are decided by exact selectivity computation, plain or batched,
+with or without the learned gate.
+
+Each query has one selection per table: two build relations R and S and the
+largest relation P, which is probed (Section 2.2: hash tables are built on
+all but the largest relation).  The optimizer needs, per query:
+  - push-down of each build-side selection: only when its selectivity is
+    below the maximum threshold tau and the table has more than min_rows
+    rows (Section 2.1);
+  - join order: the smaller filtered build relation first (Section 2.2);
+  - no push-down on the probe relation (Section 2.2), so its cardinality
+    does not change the plan.
+Latency of a query is the time from its arrival until its three
+selectivities are decided.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import esc
+
+
+@dataclass
+class GateConfig:
+    tau: float = 0.05
+    min_rows: int = 1_000_000
+    beta: float = 1.25
+    exact_probe: bool = False
+
+
+def decide(sel_r, sel_s, n_r, n_s, g: GateConfig):
+    """Plan decisions from (estimated or exact) selectivities of R and S."""
+    push_r = n_r >= g.min_rows and sel_r < g.tau
+    push_s = n_s >= g.min_rows and sel_s < g.tau
+    r_first = sel_r * n_r <= sel_s * n_s
+    return push_r, push_s, r_first
+
+
+class Workload:
+    def __init__(self, ctx, tables, queries, arrivals):
+        """tables: [R, S, P] esc.Table (device); queries: list of 3-tuples of
+        predicate descriptions; arrivals: seconds, increasing."""
+        self.ctx = ctx
+        self.tables = tables
+        self.queries = queries
+        self.arrivals = np.asarray(arrivals, np.float64)
+        self.cps = [[esc.Pred(tables[t], q[t]) for t in range(3)] for q in queries]
+        self.ws = [ctx.workspace(t, False, key=("plan", i)) for i, t in enumerate(tables)]
+
+    # --------------------------------------------------------- plain
+    def run_plain(self):
+        """Queries in arrival order; each selectivity by one esc_count."""
+        n = len(self.queries)
+        done = np.zeros(n)
+        counts = np.zeros((n, 3), np.uint64)
+        t0 = time.perf_counter()
+        for i in range(n):
+            now = time.perf_counter() - t0
+            if now < self.arrivals[i]:
+                time.sleep(self.arrivals[i] - now)
+            for t in range(3):
+                counts[i, t] = self.ctx.count(self.tables[t], self.cps[i][t], ws=self.ws[t])
+            done[i] = time.perf_counter() - t0
+        return self._report(done, counts, 3 * n, "plain")
+
+    # --------------------------------------------------------- batched (+ gate)
+    def run_batched(self, window=64, max_wait_s=1e-3, gate=None, estimators=None, gcfg: GateConfig = None):
+        """Micro-batches of arriving queries: when `window` queries are
+        pending or the oldest has waited max_wait_s, the pending selections
+        go to one batched graph launch.  With a gate, each pending selection
+        is first estimated and only the routed ones are counted exactly."""
+        n = len(self.queries)
+        done = np.zeros(n)
+        counts = np.zeros((n, 3), np.uint64)
+        est = np.full((n, 3), np.nan)
+        routed = np.zeros((n, 3), bool)
+        nrows = [t.nrows for t in self.tables]
+        t0 = time.perf_counter()
+        i = 0
+        exact_preds = 0
+        while i < n:
+            now = time.perf_counter() - t0
+            if now < self.arrivals[i]:
+                time.sleep(self.arrivals[i] - now)
+                now = time.perf_counter() - t0
+            # pending = arrived queries from i on, up to `window`
+            j = i
+            while j < n and j - i < window and self.arrivals[j] <= now:
+                j += 1
+            if j - i < window and j < n:
+                # wait for more arrivals until the oldest has waited max_wait_s
+                deadline = self.arrivals[i] + max_wait_s
+                while j < n and j - i < window and self.arrivals[j] <= deadline:
+                    if now < self.arrivals[j]:
+                        time.sleep(max(0.0, min(self.arrivals[j], deadline) - now))
+                        now = time.perf_counter() - t0
+                    if self.arrivals[j] <= now:
+                        j += 1
+                    else:
+                        break
+                if now < deadline and j - i < window:
+                    time.sleep(max(0.0, deadline - now))
+                    now = time.perf_counter() - t0
+                    while j < n and j - i < window and self.arrivals[j] <= now:
+                        j += 1
+            sel = [(q, t) for q in range(i, j) for t in range(3)]
+            need = sel
+            if gate is not None:
+                need = []
+                for t in range(3):
+                    qs = [q for q in range(i, j)]
+                    x = estimators[t].features([self.cps[q][t] for q in qs])
+                    yh = estimators[t].predict(x)
+                    est[i:j, t] = yh
+                    if t < 2:
+                        r = esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows)
+                        routed[i:j, t] |= r
+                    elif gcfg.exact_probe:
+                        routed[i:j, t] = True
+                for q in range(i, j):
+                    if esc.gate_join_pair(est[q, 0], nrows[0], est[q, 1], nrows[1], gcfg.beta):
+                        routed[q, 0] = routed[q, 1] = True
+                need = [(q, t) for q in range(i, j) for t in range(3) if routed[q, t]]
+            if need:
+                b = esc.Batch(self.ctx, self.tables, [self.cps[q][t] for q, t in need], [t for _, t in need],
+                              chunk_rows=1 << 21)
+                c = b.count()
+                for (q, t), v in zip(need, c):
+                    counts[q, t] = v
+                exact_preds += len(need)
+            done[i:j] = time.perf_counter() - t0
+            i = j
+        rep = self._report(done, counts, 3 * n, "batched" if gate is None else "batched+gate")
+        rep["exact_fraction"] = exact_preds / (3.0 * n)
+        rep["est"] = est
+        rep["routed"] = routed
+        return rep
+
+    def _report(self, done, counts, npreds, name):
+        lat = (done - self.arrivals) * 1e3
+        makespan = float(done[-1] - 0.0) if len(done) else 0.0
+        return {"mode": name, "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "predicates_per_s": npreds / max(makespan - float(self.arrivals[0]), 1e-9),
+                "makespan_s": makespan, "counts": counts}
+
+
+def plans(sel, nrows, gcfg):
+    """Plan decisions of every query from a (n, 3) selectivity array."""
+    out = []
+    for s in sel:
+        out.append(decide(s[0], s[1], nrows[0], nrows[1], gcfg))
+    return out
