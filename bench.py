@@ -81,7 +81,18 @@ def main():
     ap.add_argument("--rows", type=int, default=60_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--learned", action="store_true", help="learned-gate workload (100M x 6, 200K labels)")
+    ap.add_argument("--planning", action="store_true", help="planning workload (1,000 three-table queries)")
+    ap.add_argument("--copy-ref", action="store_true", help="1 GiB device copy (counter calibration)")
+    ap.add_argument("--train-preds", type=int, default=200_000)
+    ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
+    if args.copy_ref:
+        return copy_reference()
+    if args.learned:
+        return learned_workload(args)
+    if args.planning:
+        return planning_workload(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
                                    "but not implemented, so --gpus must be 1"}))
@@ -136,16 +147,18 @@ def main():
     ms = el / args.steps * 1e3
     value = step_bytes / (el / args.steps) / 1e9
 
-    # dominant kernel: the count scan, launched back to back on `stream` and
-    # bracketed by HIP events on that stream (cold: a 1 GiB write between
-    # predicates evicts the 256 MB last-level cache)
+    # dominant kernel: the count scan, timed per launch with HIP events on the
+    # stream it runs on; before each launch a 1 GiB read (a reduction over an
+    # unrelated buffer) evicts the 256 MB last-level cache without leaving
+    # dirty lines behind, and the device is synchronised
     log("count-kernel timing")
     dcount = torch.zeros(len(cps), dtype=torch.int64, device=dev)
-    scratch = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+    scratch = torch.ones(1 << 28, dtype=torch.int32, device=dev)
     cws = ctx.workspace(dt, False, key="count")
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in cps]
     for i, p in enumerate(cps):
-        scratch.fill_(i)
+        scratch.sum()
+        torch.cuda.synchronize()
         ev[i][0].record(stream)
         ctx.count_async(dt, p, dcount[i:i + 1], cws, stream=stream)
         ev[i][1].record(stream)
@@ -274,3 +287,143 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=300):
 
 if __name__ == "__main__":
     main()
+
+
+def copy_reference():
+    """A plain 1 GiB device-to-device copy, for calibrating HBM byte counters."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 3}))
+
+
+def learned_workload(args):
+    """Learned gate on a 100M x 6 correlated / skewed table: exact labels by
+    the batched scan, GPU training, q-error on held-out batches of 4,096,
+    routing and exact fallback."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc, learned
+    from oracle import scan
+    torch.cuda.init()
+    dev = "cuda:0"
+    ctx = esc.Context(0)
+    n = 100_000_000
+    log("learned: table")
+    t = dg.table_learned(n, device=dev)
+    dt = esc.Table(t.nrows, t.dtypes, t.cols)
+    cmin = [c.min().item() for c in t.cols]
+    cmax = [c.max().item() for c in t.cols]
+    ntrain, nval, ntest = args.train_preds, 8192, 4096
+    log("learned: predicates")
+    t0 = time.perf_counter()
+    specs = dg.preds_mixed(t, ntrain + nval + ntest, seed=dg.pred_seed(3))
+    cps = [esc.Pred(dt, p) for p in specs]
+    gen_s = time.perf_counter() - t0
+    log("learned: labels")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    counts = learned.exact_counts(ctx, dt, cps)
+    label_s = time.perf_counter() - t0
+    log("learned: features + training")
+    x = esc.featurize(dt, cps, cmin, cmax)
+    y = learned.labels(counts, n)
+    tr, va, te = slice(0, ntrain), slice(ntrain, ntrain + nval), slice(ntrain + nval, None)
+    est = learned.Estimator(ctx, dt, cmin, cmax, dg.mlp_init(dg.MLP_SEED))
+    loss, train_s = est.train(x[tr], y[tr], epochs=30, batch=1024, lr=1e-3, order_seed=dg.MLP_SEED)
+    beta = learned.validation_beta(est.predict(x[va]), counts[va], n)
+    xt = torch.from_numpy(x[te]).to(dev)
+    out = torch.empty(ntest, dtype=torch.float32, device=dev)
+    for _ in range(5):
+        est.mlp.predict(xt, out)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        est.mlp.predict(xt, out)
+    ev1.record()
+    torch.cuda.synchronize()
+    infer_us = ev0.elapsed_time(ev1) / 20 * 1e3
+    yhat = out.cpu().numpy()
+    q = learned.q_error(learned.c_hat(yhat, n), counts[te], n)
+    route = esc.gate_pushdown(yhat, n, 0.05, beta, 1_000_000)
+    idx = np.flatnonzero(route) + te.start
+    exact = learned.exact_counts(ctx, dt, [cps[i] for i in idx]) if len(idx) else np.zeros(0, np.uint64)
+    host = t.host()
+    rng = np.random.default_rng(0)
+    check = [int(i) for i in rng.choice(len(counts), 300, replace=False)] + [int(i) for i in idx[:100]]
+    oracle_errors = sum(int(counts[i]) != scan.count(host, specs[i]) for i in check)
+    flops = 4096 * 2 * (64 * 256 + 2 * 256 * 256 + 256)
+    print(json.dumps({
+        "workload": "learned gate: 100M x 6 table, %d training predicates, held-out batch of 4096" % ntrain,
+        "label_s": round(label_s, 2), "label_row_predicates_per_s": round(len(cps) * n / label_s, 1),
+        "train_s": round(train_s, 2), "epochs": 30, "final_loss": float(np.mean(loss[-50:])),
+        "inference_us_per_4096": round(infer_us, 1), "inference_tflops": round(flops / (infer_us * 1e-6) / 1e12, 3),
+        "qerror_median": float(np.median(q)), "qerror_p90": float(np.quantile(q, 0.9)),
+        "qerror_p99": float(np.quantile(q, 0.99)), "qerror_max": float(q.max()), "beta": beta,
+        "routed_fraction": float(route.mean()), "routed_count_errors": int((exact != counts[idx]).sum()),
+        "oracle_checked": len(check), "oracle_errors": oracle_errors, "predicate_gen_s": round(gen_s, 1)}),
+        flush=True)
+
+
+def planning_workload(args):
+    """1,000 arriving three-table queries (10M / 100M / 1B rows): plain
+    per-selection counts vs micro-batched graph launches vs batched + gate."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc, learned, planning
+    torch.cuda.init()
+    dev = "cuda:0"
+    ctx = esc.Context(0)
+    log("planning: tables")
+    tabs = dg.tables_planning(device=dev)
+    dts = [esc.Table(t.nrows, t.dtypes, t.cols) for t in tabs]
+    nq = args.queries
+    qs = [dg.preds_mixed(t, nq, seed=dg.pred_seed(4) + i, min_conj=2, max_conj=6) for i, t in enumerate(tabs)]
+    queries = list(zip(*qs))
+    arrivals = dg.poisson_arrivals(nq, 2000.0, seed=dg.pred_seed(4))
+    ests = []
+    train_n = [100_000, 100_000, 20_000]
+    t0 = time.perf_counter()
+    for i, (t, dt) in enumerate(zip(tabs, dts)):
+        log(f"planning: estimator {i}")
+        specs = dg.preds_mixed(t, train_n[i], seed=dg.pred_seed(4) + 100 + i, min_conj=2, max_conj=6)
+        cps = [esc.Pred(dt, p) for p in specs]
+        cnt = learned.exact_counts(ctx, dt, cps)
+        cmin = [c.min().item() for c in t.cols]
+        cmax = [c.max().item() for c in t.cols]
+        e = learned.Estimator(ctx, dt, cmin, cmax, dg.mlp_init(dg.MLP_SEED))
+        x = e.features(cps)
+        e.train(x, learned.labels(cnt, t.nrows), epochs=20, batch=1024, lr=1e-3, order_seed=11 + i)
+        ests.append(e)
+    offline_s = time.perf_counter() - t0
+    w = planning.Workload(ctx, dts, queries, arrivals)
+    log("planning: plain")
+    plain = w.run_plain()
+    log("planning: batched")
+    batched = w.run_batched()
+    gcfg = planning.GateConfig(beta=1.5)
+    log("planning: batched + gate")
+    gated = w.run_batched(gate=True, estimators=ests, gcfg=gcfg)
+    gated_p = w.run_batched(gate=True, estimators=ests,
+                            gcfg=planning.GateConfig(beta=1.5, exact_probe=True))
+    r = gated["routed"]
+    exact_sel = plain["counts"] / np.array([t.nrows for t in tabs], np.float64)
+    est_sel = np.where(r, gated["counts"] / np.array([t.nrows for t in tabs], np.float64), np.exp(gated["est"]))
+    agree = np.mean([a == b for a, b in zip(planning.plans(exact_sel, [t.nrows for t in tabs], gcfg),
+                                            planning.plans(est_sel, [t.nrows for t in tabs], gcfg))])
+    strip = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()
+                       if k not in ("counts", "est", "routed")}
+    print(json.dumps({
+        "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s",
+        "plain": strip(plain), "batched": strip(batched), "batched_gate": strip(gated),
+        "batched_gate_exact_probe": strip(gated_p),
+        "gate_speedup_vs_plain": round(gated["predicates_per_s"] / plain["predicates_per_s"], 2),
+        "batched_speedup_vs_plain": round(batched["predicates_per_s"] / plain["predicates_per_s"], 2),
+        "routed_count_errors": int((gated["counts"][r] != plain["counts"][r]).sum()),
+        "batched_count_errors": int((batched["counts"] != plain["counts"]).sum()),
+        "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1)}), flush=True)

@@ -47,7 +47,7 @@ typedef enum {
     ESC_ERR_HIP = -5,          /* a HIP runtime call failed (message has the HIP error) */
     ESC_ERR_OOM = -6,          /* host or device allocation failed, or workspace too small */
     ESC_ERR_UNSUPPORTED = -7,  /* valid but beyond the compiled limits (see ESC_MAX_*) */
-    ESC_ERR_TIMEOUT = -8       /* a kernel's bounded wait expired; results are undefined */
+    ESC_ERR_TIMEOUT = -8       /* reserved: a bounded device wait expired */
 } esc_status;
 
 /* Limits of one compiled predicate. */
@@ -176,13 +176,16 @@ int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);
  * Workspace: device memory of at least esc_workspace_size() bytes, 256-byte
  * aligned, zero-filled before its first use (esc_workspace_init does that);
  * every successful call leaves it ready for the next call.  Calls that may
- * overlap in time (different streams) need distinct workspaces. */
+ * overlap in time (different streams) need distinct workspaces.  A workspace
+ * sized for materialization (materialize = 1) also receives, from every
+ * esc_count, the qualifying-row count of each tile of rows. */
 int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes);
 int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream);
 
 /* Exact COUNT(*) of the selection (Section 2: the selectivity sub-query
  * with a temporary COUNT aggregate).  Blocks until the count is on the
- * host. */
+ * host.  With a materialization-sized workspace the per-tile counts are
+ * left in it for a following esc_materialize of the same predicate. */
 int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
               void *dev_ws, size_t ws_bytes, void *stream, uint64_t *out_count);
 
@@ -199,7 +202,13 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
  * Blocks until the count is on the host.  When the count exceeds
  * `capacity`, the first `capacity` rows are written, *out_count receives the
  * full count and ESC_ERR_CAPACITY is returned.  0 <= nproj <= ESC_MAX_PROJ;
- * dev_rowids may be NULL when only projections are wanted. */
+ * dev_rowids may be NULL when only projections are wanted.
+ * When the last scan on this workspace was an esc_count of the same table
+ * handle and predicate handle (the ESC flow: count, decide, materialize),
+ * its per-tile counts are reused and the columns are read once more only;
+ * this assumes the table's contents did not change in between (call
+ * esc_workspace_init after changing them).  Otherwise the call counts
+ * first.  Needs a workspace of esc_workspace_size(t, 1, ...) bytes. */
 int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                     const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
                     void *const *dev_proj_out, uint64_t capacity,
@@ -225,9 +234,13 @@ typedef struct {
 int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,
                      const esc_pred *const *preds, const int32_t *pred_table, int npreds,
                      const esc_batch_opts *opts, void *stream, esc_batch **out);
-/* New predicates for the same tables (pred_table unchanged); recompiles the
- * work list if the predicates' column sets changed. */
-int esc_batch_update(esc_batch *b, const esc_pred *const *preds, int npreds, void *stream);
+/* New predicates over the same tables: pred_table gives the owner of each
+ * (NULL keeps the previous owners, then npreds must not change).  The work
+ * list is rebuilt; the captured graph is reused whenever its buffers and
+ * counter capacity still fit, so a new predicate set of a similar size costs
+ * a few host-to-device copies. */
+int esc_batch_update(esc_batch *b, const esc_pred *const *preds, const int32_t *pred_table, int npreds,
+                     void *stream);
 /* Launches the graph and waits; out_counts[i] = exact count of preds[i]. */
 int esc_batch_count(esc_batch *b, void *stream, uint64_t *out_counts);
 /* The configuration in use (after tuning). */

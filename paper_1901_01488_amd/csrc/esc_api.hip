@@ -21,7 +21,14 @@ namespace esc {
 
 int hip_fail(hipError_t e, const char *what)
 {
+    (void)hipGetLastError();   // do not leave the error for the caller's next HIP call
     return fail(ESC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int set_device(int device)
+{
+    hipError_t e = hipSetDevice(device);
+    return e == hipSuccess ? ESC_OK : hip_fail(e, "hipSetDevice");
 }
 
 static std::mutex g_occ_mu;
@@ -178,7 +185,7 @@ int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
 int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream)
 {
     if (!ctx || !dev_ws || ws_bytes < sizeof(WsHeader)) return fail(ESC_ERR_INVALID, "bad workspace");
-    (void)hipSetDevice(ctx->device);
+    if (int rc = set_device(ctx->device)) return rc;
     forget_tiles(ctx, dev_ws);
     launch_zero((unsigned long long *)dev_ws, (int64_t)(ws_bytes / 8), (hipStream_t)stream);
     hipError_t e = hipGetLastError();
@@ -192,9 +199,12 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
 {
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
     if (rc) return rc;
-    (void)hipSetDevice(ctx->device);
+    if ((rc = set_device(ctx->device))) return rc;
     const Program &P = p->prog;
-    if ((P.flags & (P_ALWAYS_FALSE | P_ALWAYS_TRUE)) || t->nrows == 0) {
+    // a constant predicate needs no scan, unless per-tile counts are wanted
+    // (an always-true program has no instructions and counts the valid rows)
+    const bool constant = (P.flags & P_ALWAYS_FALSE) || ((P.flags & P_ALWAYS_TRUE) && !need_tiles);
+    if (constant || t->nrows == 0) {
         const unsigned long long v = (P.flags & P_ALWAYS_TRUE) ? (unsigned long long)t->nrows : 0ull;
         hipLaunchKernelGGL(store_u64_kernel, dim3(1), dim3(1), 0, s, dev_out, v);
     } else {
@@ -269,7 +279,7 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
         *out_count = 0;
         return ESC_OK;
     }
-    (void)hipSetDevice(ctx->device);
+    if ((rc = set_device(ctx->device))) return rc;
     hipStream_t s = (hipStream_t)stream;
     WsHeader *h = (WsHeader *)dev_ws;
     uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);

@@ -81,7 +81,7 @@ __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &i
 
 template <int RPT>
 __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
-                                                           const BatchItem *__restrict__ items, int nitems,
+                                                           const BatchItem *__restrict__ items,
                                                            const Program *__restrict__ progs,
                                                            const int32_t *__restrict__ pred_ids,
                                                            unsigned long long *counts, unsigned int *queue)
@@ -89,6 +89,7 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
     constexpr int NW = kScanBlock / 64;
     __shared__ uint32_t s_cnt[kMaxGroup][NW];
     __shared__ int s_item;
+    const int nitems = (int)queue[1];   // written by the host with the plan
     for (int i = threadIdx.x; i < kMaxGroup * NW; i += kScanBlock) (&s_cnt[0][0])[i] = 0;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
     }
 }
 
-typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, int, const Program *, const int32_t *,
+typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
 static BatchFn batch_fn(int rpt) { return rpt == 16 ? batch_kernel<16> : batch_kernel<8>; }
@@ -151,6 +152,7 @@ struct Plan {
 
 struct esc_batch {
     esc_ctx *ctx = nullptr;
+    int device = 0;                      // kept so that destruction never touches ctx
     std::vector<TableInfo> tables;
     std::vector<int32_t> pred_table;
     std::vector<Program> src;            // compiled programs as given
@@ -163,7 +165,10 @@ struct esc_batch {
     Program *d_progs = nullptr;
     int32_t *d_pred_ids = nullptr;
     unsigned long long *d_counts = nullptr;
-    unsigned int *d_queue = nullptr;
+    unsigned int *d_queue = nullptr;     // [0] next item, [1] number of items
+    size_t cap_counts = 0;               // predicates the counters and the graph cover
+    const void *graph_ptrs[5] = {};      // buffers the captured graph refers to
+    int graph_rpt = 0;
     size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
     unsigned long long *h_counts = nullptr;   // pinned
     int nitems = 0;
@@ -271,7 +276,10 @@ void destroy_graph(esc_batch *b)
     b->graph = nullptr;
 }
 
-// Uploads a plan and captures zero -> kernel -> copy into a graph.
+// Uploads a plan; captures zero -> kernel -> copy into a graph unless the
+// graph of an earlier plan still fits (same buffers, kernel shape and counter
+// capacity): the item count lives in device memory, so a new plan of the
+// same shape costs a few small copies and no capture.
 int install(esc_batch *b, const esc_batch_opts &o)
 {
     Plan plan;
@@ -281,7 +289,23 @@ int install(esc_batch *b, const esc_batch_opts &o)
     if ((rc = ensure(b->d_items, b->cap_items, plan.items.size()))) return rc;
     if ((rc = ensure(b->d_progs, b->cap_progs, plan.progs.size()))) return rc;
     if ((rc = ensure(b->d_pred_ids, b->cap_ids, plan.pred_ids.size()))) return rc;
+    const size_t npreds = b->pred_table.size();
+    if (npreds > b->cap_counts) {
+        const size_t cap = std::max(npreds, b->cap_counts * 3 / 2);
+        if (b->d_counts) (void)hipFree(b->d_counts);
+        if (b->h_counts) (void)hipHostFree(b->h_counts);
+        b->d_counts = nullptr;
+        b->h_counts = nullptr;
+        b->cap_counts = 0;
+        hipError_t e;
+        if ((e = hipMalloc((void **)&b->d_counts, cap * sizeof(unsigned long long))) != hipSuccess ||
+            (e = hipHostMalloc((void **)&b->h_counts, cap * sizeof(unsigned long long), hipHostMallocDefault)) !=
+                hipSuccess)
+            return fail(ESC_ERR_OOM, "batch counters: %s", hipGetErrorString(e));
+        b->cap_counts = cap;
+    }
     hipStream_t s = b->cap_stream;
+    const unsigned int nitems = (unsigned int)plan.items.size();
     if ((rc = hipchk(hipMemcpyAsync(b->d_groups, plan.groups.data(), plan.groups.size() * sizeof(BatchGroup),
                                     hipMemcpyHostToDevice, s), "upload groups"))) return rc;
     if ((rc = hipchk(hipMemcpyAsync(b->d_items, plan.items.data(), plan.items.size() * sizeof(BatchItem),
@@ -290,32 +314,36 @@ int install(esc_batch *b, const esc_batch_opts &o)
                                     hipMemcpyHostToDevice, s), "upload programs"))) return rc;
     if ((rc = hipchk(hipMemcpyAsync(b->d_pred_ids, plan.pred_ids.data(), plan.pred_ids.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, s), "upload ids"))) return rc;
+    if ((rc = hipchk(hipMemcpyAsync(b->d_queue + 1, &nitems, sizeof nitems, hipMemcpyHostToDevice, s),
+                     "upload item count"))) return rc;
     if ((rc = hipchk(hipStreamSynchronize(s), "upload sync"))) return rc;
-    b->nitems = (int)plan.items.size();
+    b->nitems = (int)nitems;
     BatchFn fn = batch_fn(o.rows_per_thread);
     int occ = occupancy((const void *)fn, kScanBlock, 0);
     int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
-    int64_t grid = (int64_t)b->ctx->num_cus * bpc;
-    if (grid > b->nitems) grid = b->nitems;
-    if (grid < 1) grid = 1;
-    b->grid = (int)grid;
+    const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
+    b->opts = o;
+    b->opts.blocks_per_cu = bpc;
+    const void *ptrs[5] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts};
+    const bool reuse = b->exec && grid == b->grid && b->graph_rpt == o.rows_per_thread &&
+                       memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
+    if (reuse) return ESC_OK;
     destroy_graph(b);
-    const int npreds = (int)b->pred_table.size();
+    b->grid = grid;
+    const int cap = (int)b->cap_counts;
     if ((rc = hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture"))) return rc;
-    hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(1, std::min(64, (npreds + 255) / 256))), dim3(256), 0, s,
-                       b->d_counts, npreds, b->d_queue);
-    if (b->nitems > 0)
-        hipLaunchKernelGGL(fn, dim3(b->grid), dim3(kScanBlock), 0, s, b->d_groups, b->d_items, b->nitems,
-                           b->d_progs, b->d_pred_ids, b->d_counts, b->d_queue);
-    (void)hipMemcpyAsync(b->h_counts, b->d_counts, std::max(npreds, 1) * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, s);
+    hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(1, std::min(64, (cap + 255) / 256))), dim3(256), 0, s,
+                       b->d_counts, cap, b->d_queue);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kScanBlock), 0, s, b->d_groups, b->d_items, b->d_progs, b->d_pred_ids,
+                       b->d_counts, b->d_queue);
+    (void)hipMemcpyAsync(b->h_counts, b->d_counts, cap * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess) return hip_fail(e, "end capture");
     b->graph = g;
     if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
-    b->opts = o;
-    b->opts.blocks_per_cu = bpc;
+    memcpy(b->graph_ptrs, ptrs, sizeof ptrs);
+    b->graph_rpt = o.rows_per_thread;
     return ESC_OK;
 }
 
@@ -480,7 +508,8 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     esc_batch *b = new (std::nothrow) esc_batch;
     if (!b) return fail(ESC_ERR_OOM, "out of host memory");
     b->ctx = ctx;
-    (void)hipSetDevice(ctx->device);
+    b->device = ctx->device;
+    if (int rc0 = set_device(ctx->device)) { delete b; return rc0; }
     int rc = ESC_OK;
     for (int t = 0; t < ntables; t++) {
         if (!tables[t] || !tables[t]->has_data()) { free_batch(b); return fail(ESC_ERR_INVALID, "table %d has no device columns", t); }
@@ -492,9 +521,7 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     if ((rc = set_preds(b, preds, npreds))) { free_batch(b); return rc; }
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) { free_batch(b); return hip_fail(e, "stream"); }
-    if ((e = hipMalloc((void **)&b->d_counts, npreds * sizeof(unsigned long long))) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_queue, 256)) != hipSuccess ||
-        (e = hipHostMalloc((void **)&b->h_counts, npreds * sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess) {
+    if ((e = hipMalloc((void **)&b->d_queue, 256)) != hipSuccess) {
         free_batch(b);
         return fail(ESC_ERR_OOM, "batch allocation: %s", hipGetErrorString(e));
     }
@@ -509,12 +536,20 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     return ESC_OK;
 }
 
-int esc_batch_update(esc_batch *b, const esc_pred *const *preds, int npreds, void *stream)
+int esc_batch_update(esc_batch *b, const esc_pred *const *preds, const int32_t *pred_table, int npreds,
+                     void *stream)
 {
     (void)stream;
-    if (!b || !preds) return fail(ESC_ERR_INVALID, "null argument");
-    if (npreds != (int)b->pred_table.size()) return fail(ESC_ERR_INVALID, "update must keep the number of predicates");
-    (void)hipSetDevice(b->ctx->device);
+    if (!b || !preds || npreds <= 0) return fail(ESC_ERR_INVALID, "null argument or empty batch");
+    if (!pred_table && npreds != (int)b->pred_table.size())
+        return fail(ESC_ERR_INVALID, "a different number of predicates needs pred_table");
+    if (int rc0 = set_device(b->device)) return rc0;
+    if (pred_table) {
+        for (int p = 0; p < npreds; p++)
+            if (pred_table[p] < 0 || pred_table[p] >= (int)b->tables.size())
+                return fail(ESC_ERR_INVALID, "pred_table[%d] out of range", p);
+        b->pred_table.assign(pred_table, pred_table + npreds);
+    }
     int rc = set_preds(b, preds, npreds);
     if (rc) return rc;
     return install(b, b->opts);
@@ -523,7 +558,7 @@ int esc_batch_update(esc_batch *b, const esc_pred *const *preds, int npreds, voi
 int esc_batch_count(esc_batch *b, void *stream, uint64_t *out_counts)
 {
     if (!b || !out_counts) return fail(ESC_ERR_INVALID, "null argument");
-    (void)hipSetDevice(b->ctx->device);
+    if (int rc = set_device(b->device)) return rc;
     return run(b, (hipStream_t)stream, out_counts);
 }
 
@@ -537,7 +572,7 @@ int esc_batch_get_opts(const esc_batch *b, esc_batch_opts *out)
 int esc_batch_destroy(esc_batch *b)
 {
     if (!b) return ESC_OK;
-    (void)hipSetDevice(b->ctx->device);
+    (void)set_device(b->device);
     free_batch(b);
     return ESC_OK;
 }

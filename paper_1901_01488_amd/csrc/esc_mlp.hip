@@ -264,6 +264,7 @@ using namespace esc;
 
 struct esc_mlp {
     esc_ctx *ctx = nullptr;
+    int device = 0;                                                  // destruction never touches ctx
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // kNParams each
     bf16_t *wb = nullptr;                                            // kNBf
     bf16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
@@ -365,8 +366,7 @@ void free_mlp(esc_mlp *m)
 int check_mlp(const esc_mlp *m)
 {
     if (!m) return fail(ESC_ERR_INVALID, "null mlp handle");
-    (void)hipSetDevice(m->ctx->device);
-    return ESC_OK;
+    return set_device(m->device);
 }
 
 }  // namespace
@@ -376,10 +376,11 @@ extern "C" {
 int esc_mlp_create(esc_ctx *ctx, esc_mlp **out)
 {
     if (!ctx || !out) return fail(ESC_ERR_INVALID, "null argument");
-    (void)hipSetDevice(ctx->device);
+    if (int rc0 = set_device(ctx->device)) return rc0;
     esc_mlp *m = new (std::nothrow) esc_mlp;
     if (!m) return fail(ESC_ERR_OOM, "out of host memory");
     m->ctx = ctx;
+    m->device = ctx->device;
     struct { void **p; size_t bytes; } allocs[] = {
         {(void **)&m->p, kNParams * 4}, {(void **)&m->g, kNParams * 4}, {(void **)&m->m, kNParams * 4},
         {(void **)&m->v, kNParams * 4}, {(void **)&m->wb, kNBf * 2}, {(void **)&m->a0, kMaxRows * kIn * 2},
@@ -405,7 +406,7 @@ int esc_mlp_create(esc_ctx *ctx, esc_mlp **out)
 int esc_mlp_destroy(esc_mlp *m)
 {
     if (!m) return ESC_OK;
-    (void)hipSetDevice(m->ctx->device);
+    (void)set_device(m->device);
     free_mlp(m);
     return ESC_OK;
 }

@@ -9,16 +9,18 @@ struct esc_ctx {
     int device = 0;
     int num_cus = 0;
     unsigned long long *pinned = nullptr;   // 4 KiB of pinned host memory for read-backs
-    int count_variant = 1;                  // count kernel shape (see count_fn)
+    int count_variant = 3;                  // count kernel shape (see count_fn): 32 rows per lane
     int rpt_mat = 8;                        // rows per thread of the materialize kernel
     int nt = 1;                             // streaming loads in the scans
-    int bpc = 0;                            // count-kernel blocks per CU (0: occupancy)
+    int bpc = 1;                            // count-kernel blocks per CU (0: occupancy)
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)
 };
 
 namespace esc {
 
 int hip_fail(hipError_t e, const char *what);
+// Makes `device` current; on failure clears HIP's sticky error and reports it.
+int set_device(int device);
 int occupancy(const void *fn, int block, int dyn_lds);
 ColPtrs slot_ptrs(const esc_table *t, const Program &P, int nt);
 

@@ -104,34 +104,69 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
 // ------------------------------------------------------------------ scan
 
 // Exclusive scan of m per-tile counts into offsets[0..m]; offsets[m] is the
-// total, also stored in ws->result.  One block; each thread scans a
-// contiguous stretch, then the stretch totals are scanned in LDS.
+// total, also stored in ws->result.  One block of 1024 threads walks the
+// counts in rounds of 16384: each thread takes 16 consecutive counts (four
+// 16-byte loads, coalesced across the block), the thread totals are scanned
+// with wave shuffles and a 16-entry LDS pass, and a carry links the rounds.
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *counts, int64_t m, uint32_t *offsets,
                                                     WsHeader *ws)
 {
-    __shared__ uint32_t s[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t lo = t * per < m ? t * per : m;
-    const int64_t hi = lo + per < m ? lo + per : m;
-    uint32_t sum = 0;
-    for (int64_t i = lo; i < hi; i++) sum += counts[i];
-    s[t] = sum;
+    constexpr int PER = 16, NT = 1024, NWV = NT / 64;
+    __shared__ uint32_t s_wave[NWV];
+    __shared__ uint32_t s_carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) s_carry = 0;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t x = t >= o ? s[t - o] : 0u;
+    for (int64_t r0 = 0; r0 < m; r0 += (int64_t)PER * NT) {
+        const int64_t i0 = r0 + (int64_t)t * PER;
+        uint32_t c[PER];
+        if (i0 + PER <= m) {
+#pragma unroll
+            for (int q = 0; q < PER / 4; q++) {
+                const u32x4 v = *(const u32x4 *)(counts + i0 + 4 * q);
+                c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PER; q++) c[q] = i0 + q < m ? counts[i0 + q] : 0u;
+        }
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < PER; q++) sum += c[q];
+        // inclusive scan of the thread sums inside the wave
+        uint32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += x;
+        }
+        if (lane == 63) s_wave[wave] = inc;
         __syncthreads();
-        s[t] += x;
+        uint32_t before = s_carry;
+        for (int w = 0; w < wave; w++) before += s_wave[w];
+        uint32_t run = before + inc - sum;   // exclusive prefix of this thread's first count
+        uint32_t o16[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) { o16[q] = run; run += c[q]; }
+        if (i0 + PER <= m) {
+#pragma unroll
+            for (int q = 0; q < PER / 4; q++) {
+                u32x4 v;
+                v.x = o16[4 * q]; v.y = o16[4 * q + 1]; v.z = o16[4 * q + 2]; v.w = o16[4 * q + 3];
+                *(u32x4 *)(offsets + i0 + 4 * q) = v;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PER; q++)
+                if (i0 + q < m) offsets[i0 + q] = o16[q];
+        }
+        __syncthreads();   // every thread has read s_wave and s_carry
+        if (t == NT - 1) s_carry = run;
         __syncthreads();
     }
-    uint32_t run = s[t] - sum;   // exclusive prefix of this stretch
-    for (int64_t i = lo; i < hi; i++) {
-        offsets[i] = run;
-        run += counts[i];
-    }
-    if (t == 1023) {
-        offsets[m] = s[1023];
-        ws->result = s[1023];
+    if (t == 0) {
+        offsets[m] = s_carry;
+        ws->result = s_carry;
     }
 }
 

@@ -96,7 +96,7 @@ def lib():
             "esc_materialize": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, P(u64)],
                                 ctypes.c_int),
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
-            "esc_batch_update": ([vp, vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
             "esc_batch_destroy": ([vp], ctypes.c_int),
@@ -361,10 +361,13 @@ class Batch:
         check(lib().esc_batch_count(self.h, _stream_handle(stream), out.ctypes.data))
         return out
 
-    def update(self, preds, stream=None):
+    def update(self, preds, owner=None, stream=None):
         self.preds = list(preds)
         ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
-        check(lib().esc_batch_update(self.h, ph, len(self.preds), _stream_handle(stream)))
+        if owner is not None:
+            self.owner = np.ascontiguousarray(owner, np.int32)
+        check(lib().esc_batch_update(self.h, ph, self.owner.ctypes.data if owner is not None else None,
+                                     len(self.preds), _stream_handle(stream)))
 
     def opts(self):
         o = BatchOpts()

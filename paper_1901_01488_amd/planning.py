@@ -51,6 +51,7 @@ class Workload:
         self.arrivals = np.asarray(arrivals, np.float64)
         self.cps = [[esc.Pred(tables[t], q[t]) for t in range(3)] for q in queries]
         self.ws = [ctx.workspace(t, False, key=("plan", i)) for i, t in enumerate(tables)]
+        self.batch = None   # one batched handle, re-planned per micro-batch
 
     # --------------------------------------------------------- plain
     def run_plain(self):
@@ -127,9 +128,14 @@ class Workload:
                         routed[q, 0] = routed[q, 1] = True
                 need = [(q, t) for q in range(i, j) for t in range(3) if routed[q, t]]
             if need:
-                b = esc.Batch(self.ctx, self.tables, [self.cps[q][t] for q, t in need], [t for _, t in need],
-                              chunk_rows=1 << 21)
-                c = b.count()
+                preds = [self.cps[q][t] for q, t in need]
+                owners = [t for _, t in need]
+                if self.batch is None:
+                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16,
+                                           chunk_rows=1 << 21)
+                else:
+                    self.batch.update(preds, owners)
+                c = self.batch.count()
                 for (q, t), v in zip(need, c):
                     counts[q, t] = v
                 exact_preds += len(need)

@@ -27,8 +27,8 @@ def small_batch():
     return tabs, preds, owner
 
 
-@pytest.mark.parametrize("opts", [dict(), dict(rows_per_thread=4), dict(group=5, chunk_rows=4096),
-                                  dict(group=1, chunk_rows=1 << 20, rows_per_thread=4), dict(blocks_per_cu=1)])
+@pytest.mark.parametrize("opts", [dict(), dict(rows_per_thread=16), dict(group=5, chunk_rows=4096),
+                                  dict(group=1, chunk_rows=1 << 20, rows_per_thread=16), dict(blocks_per_cu=1)])
 def test_batched_equals_oracle_small(ctx, small_batch, opts):
     tabs, preds, owner = small_batch
     dts = [esc.device_table(t) for t in tabs]
@@ -70,7 +70,7 @@ def test_autotune_small(ctx, small_batch):
     want = [scan.count(tabs[o], p) for p, o in zip(preds, owner)]
     assert b.count().tolist() == want
     o = b.opts()
-    assert o["rows_per_thread"] in (4, 8)
+    assert o["rows_per_thread"] in (8, 16)
 
 
 def test_batched_full_size(ctx):
@@ -96,3 +96,18 @@ def test_batched_full_size(ctx):
         if o not in host:
             host[o] = tabs[o].host()
         assert got[i] == scan.count(host[o], preds[i]), i
+
+
+def test_batched_update_changes_shape(ctx, small_batch):
+    """Re-planning with a different number of predicates and owners (the
+    micro-batch path of the planning workload) gives exact counts each time."""
+    tabs, preds, owner = small_batch
+    dts = [esc.device_table(t) for t in tabs]
+    cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    b = esc.Batch(ctx, dts, cps[:10], owner[:10])
+    rng = np.random.default_rng(21)
+    for size in (3, 40, 256, 7, 1):
+        pick = rng.choice(len(preds), size, replace=False)
+        b.update([cps[i] for i in pick], [owner[i] for i in pick])
+        want = [scan.count(tabs[owner[i]], preds[i]) for i in pick]
+        assert b.count().tolist() == want, size

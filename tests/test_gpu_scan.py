@@ -174,3 +174,22 @@ def test_star_full_size_counts_and_rows(ctx):
                 assert bool((ids[1:] > ids[:-1]).all())
             for j, o in zip(dg.STAR_PROJECTION, outs):
                 assert torch.equal(o[:n].view(torch.int32), dt.cols[j][ids.long()].view(torch.int32))
+
+
+def test_constant_predicates_materialize(ctx):
+    """Always-true and always-false predicates (folded at compile time) still
+    materialize every / no row, also on a fresh workspace."""
+    import torch
+    t = dg.table_plain(5_000, seed=83)
+    dt = esc.device_table(t)
+    for spec, want in [(("between", 1, -2**31, 2**31 - 1), t.nrows), (("lt", 1, -2**31), 0)]:
+        p = esc.Pred(dt, spec)
+        assert p.info()["constant"] != 0
+        ids = torch.full((t.nrows,), -1, dtype=torch.int32, device="cuda")
+        out = torch.zeros(t.nrows, dtype=torch.int32, device="cuda")
+        ws = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
+        assert ctx.materialize(dt, p, [2], ids, [out], t.nrows, ws=ws) == want
+        assert ctx.count(dt, p, ws=ws) == want
+        if want:
+            assert torch.equal(ids.cpu(), torch.arange(t.nrows, dtype=torch.int32))
+            assert torch.equal(out, dt.cols[2])
