@@ -227,7 +227,7 @@ typedef struct {
     int32_t block;           /* threads per block (256 or 512); 0 = default */
     int32_t rows_per_thread; /* 8 or 16; 0 = default */
     int32_t group;           /* predicates evaluated per pass over a chunk; 0 = all of the table's */
-    int32_t chunk_rows;      /* rows per work item; 0 = default */
+    int32_t chunk_rows;      /* rows per work item; 0 = about 8 items per block of the grid */
     int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
 } esc_batch_opts;
 

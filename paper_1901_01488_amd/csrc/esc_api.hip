@@ -144,15 +144,13 @@ int esc_ctx_create(int device, esc_ctx **out)
         return hip_fail(e, "hipHostMalloc");
     }
     const char *r = getenv("ESC_COUNT_VARIANT");
-    if (r && atoi(r) >= 0 && atoi(r) <= 4) c->count_variant = atoi(r);
+    if (r && (atoi(r) == 0 || atoi(r) == 1)) c->count_variant = atoi(r);
     r = getenv("ESC_NONTEMPORAL");
     if (r) c->nt = atoi(r) != 0;
     r = getenv("ESC_BLOCKS_PER_CU");
     if (r) c->bpc = atoi(r);
     r = getenv("ESC_MAT_BLOCKS_PER_CU");
     if (r) c->mat_bpc = atoi(r);
-    r = getenv("ESC_MAT_RPT");
-    if (r && (atoi(r) == 8 || atoi(r) == 16)) c->rpt_mat = atoi(r);
     *out = c;
     return ESC_OK;
 }
@@ -177,7 +175,7 @@ int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
 {
     if (!t || !bytes) return fail(ESC_ERR_INVALID, "null argument");
     size_t need = sizeof(WsHeader);
-    if (materialize) need = ws_layout(t->nrows, 8).bytes;   // the smallest wave tile needs the most slots
+    if (materialize) need = ws_layout(t->nrows, 16).bytes;   // the smallest wave tile needs the most slots
     *bytes = (need + 255) & ~(size_t)255;
     return ESC_OK;
 }
@@ -208,12 +206,12 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
         const unsigned long long v = (P.flags & P_ALWAYS_TRUE) ? (unsigned long long)t->nrows : 0ull;
         hipLaunchKernelGGL(store_u64_kernel, dim3(1), dim3(1), 0, s, dev_out, v);
     } else {
-        const int rpt = count_rpt(ctx->count_variant);
+        const int rpt = count_rpt(ctx->count_variant, p->prog.nslots);
         const WsLayout L = ws_layout(t->nrows, rpt);
         uint32_t *tiles = nullptr;
         if (ws_bytes >= L.bytes) tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
         else if (need_tiles) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, L.bytes);
-        CountFn fn = count_fn(P.nslots, ctx->count_variant);
+        CountFn fn = count_fn(P.nslots, ctx->count_variant, (P.flags & P_HAS_UDF) != 0);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
         int64_t grid = (int64_t)ctx->num_cus * (ctx->bpc > 0 ? ctx->bpc : occ);
         const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
@@ -253,8 +251,8 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
                     size_t ws_bytes, void *stream, uint64_t *out_count)
 {
     if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
-    if (!ctx || !t) return fail(ESC_ERR_INVALID, "null handle");
-    const int rpt = count_rpt(ctx->count_variant);
+    if (!ctx || !t || !p) return fail(ESC_ERR_INVALID, "null handle");
+    const int rpt = count_rpt(ctx->count_variant, p->prog.nslots);
     const WsLayout L = ws_layout(t->nrows, rpt);
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, L.bytes);
     if (rc) return rc;
@@ -292,7 +290,7 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     launch_scan(tiles, L.ntiles, offsets, h, s);
     // pass 3: write
     if (capacity > 0) {
-        WriteFn fn = write_fn(P.nslots, rpt);
+        WriteFn fn = write_fn(P.nslots, rpt, (P.flags & P_HAS_UDF) != 0);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
         int64_t grid = (int64_t)ctx->num_cus * (ctx->mat_bpc > 0 ? std::min(ctx->mat_bpc, occ) : occ);
         const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);

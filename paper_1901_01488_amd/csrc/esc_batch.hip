@@ -56,7 +56,7 @@ struct BatchItem {
 
 // The waves of a block walk the item's wave tiles independently; each wave
 // tile is loaded once and every predicate of the group runs on it.
-template <int K, int RPT>
+template <int K, int RPT, bool UDF>
 __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
                                          uint32_t (*s_cnt)[kScanBlock / 64])
 {
@@ -73,13 +73,13 @@ __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &i
         load_vals<K, RPT>(cp, base, it.r1, v);
         const uint32_t valid = valid_bits<RPT>(base, it.r1);
         for (int i = 0; i < npred; i++) {
-            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT>(progs[g.pbegin + i], v, valid)));
+            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
             if (lane_id() == 0) s_cnt[i][wave] += c;
         }
     }
 }
 
-template <int RPT>
+template <int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
                                                            const BatchItem *__restrict__ items,
                                                            const Program *__restrict__ progs,
@@ -99,14 +99,14 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
         const BatchItem it = items[item];
         const BatchGroup &g = groups[it.group];
         switch (g.K) {
-        case 1: run_item<1, RPT>(g, it, progs, s_cnt); break;
-        case 2: run_item<2, RPT>(g, it, progs, s_cnt); break;
-        case 3: run_item<3, RPT>(g, it, progs, s_cnt); break;
-        case 4: run_item<4, RPT>(g, it, progs, s_cnt); break;
-        case 5: run_item<5, RPT>(g, it, progs, s_cnt); break;
-        case 6: run_item<6, RPT>(g, it, progs, s_cnt); break;
-        case 7: run_item<7, RPT>(g, it, progs, s_cnt); break;
-        default: run_item<8, RPT>(g, it, progs, s_cnt); break;
+        case 1: run_item<1, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 2: run_item<2, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 3: run_item<3, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 4: run_item<4, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 5: run_item<5, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 6: run_item<6, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 7: run_item<7, RPT, UDF>(g, it, progs, s_cnt); break;
+        default: run_item<8, RPT, UDF>(g, it, progs, s_cnt); break;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < g.npred; i += kScanBlock) {
@@ -125,7 +125,11 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
 typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
-static BatchFn batch_fn(int rpt) { return rpt == 16 ? batch_kernel<16> : batch_kernel<8>; }
+static BatchFn batch_fn(int rpt, bool udf)
+{
+    if (rpt == 16) return udf ? batch_kernel<16, true> : batch_kernel<16, false>;
+    return udf ? batch_kernel<8, true> : batch_kernel<8, false>;
+}
 
 __global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
 {
@@ -169,6 +173,7 @@ struct esc_batch {
     size_t cap_counts = 0;               // predicates the counters and the graph cover
     const void *graph_ptrs[5] = {};      // buffers the captured graph refers to
     int graph_rpt = 0;
+    bool graph_udf = false;
     size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
     unsigned long long *h_counts = nullptr;   // pinned
     int nitems = 0;
@@ -199,13 +204,32 @@ Program remap(const Program &P, const int *gslot_of_col, int K, const int *gcols
     return Q;
 }
 
-int build_plan(const esc_batch *b, const esc_batch_opts &o, Plan &plan)
+// chunk_rows == 0 sizes the chunks so that the plan has about eight items
+// per block of the persistent grid (load balance at the end of the launch),
+// but no fewer than 8 block tiles per item (the per-item cost of the atomic
+// pop and of publishing the group's counts stays small).
+int64_t chunk_rows_for(const esc_batch *b, const esc_batch_opts &o, int gmax, int grid)
+{
+    const int tile = tile_rows(o.rows_per_thread);
+    int64_t chunk = o.chunk_rows;
+    if (chunk <= 0) {
+        int64_t rows = 0;
+        for (size_t t = 0; t < b->tables.size(); t++) {
+            int64_t np = 0;
+            for (size_t p = 0; p < b->pred_table.size(); p++) np += b->pred_table[p] == (int)t && b->constant[p] == 0;
+            rows += b->tables[t].nrows * ((np + gmax - 1) / gmax);   // a lower bound on the groups of the table
+        }
+        chunk = std::max<int64_t>(rows / (8 * (int64_t)std::max(grid, 1)), 8 * (int64_t)tile);
+        chunk = std::min<int64_t>(chunk, 1 << 21);
+    }
+    return (chunk + tile - 1) / tile * tile;
+}
+
+int build_plan(const esc_batch *b, const esc_batch_opts &o, int grid, Plan &plan)
 {
     plan = Plan{};
-    const int tile = tile_rows(o.rows_per_thread);
-    int64_t chunk = o.chunk_rows > 0 ? o.chunk_rows : 262144;
-    chunk = (chunk + tile - 1) / tile * tile;
     const int gmax = o.group > 0 ? std::min(o.group, kMaxGroup) : kMaxGroup;
+    const int64_t chunk = chunk_rows_for(b, o, gmax, grid);
     struct Cost { int64_t cost; BatchItem it; };
     std::vector<Cost> items;
     for (size_t t = 0; t < b->tables.size(); t++) {
@@ -282,8 +306,14 @@ void destroy_graph(esc_batch *b)
 // same shape costs a few small copies and no capture.
 int install(esc_batch *b, const esc_batch_opts &o)
 {
+    bool udf = false;
+    for (size_t p = 0; p < b->src.size(); p++) udf |= b->constant[p] == 0 && (b->src[p].flags & P_HAS_UDF) != 0;
+    BatchFn fn = batch_fn(o.rows_per_thread, udf);
+    const int occ = occupancy((const void *)fn, kScanBlock, 0);
+    const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
+    const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
     Plan plan;
-    int rc = build_plan(b, o, plan);
+    int rc = build_plan(b, o, grid, plan);
     if (rc) return rc;
     if ((rc = ensure(b->d_groups, b->cap_groups, plan.groups.size()))) return rc;
     if ((rc = ensure(b->d_items, b->cap_items, plan.items.size()))) return rc;
@@ -318,14 +348,10 @@ int install(esc_batch *b, const esc_batch_opts &o)
                      "upload item count"))) return rc;
     if ((rc = hipchk(hipStreamSynchronize(s), "upload sync"))) return rc;
     b->nitems = (int)nitems;
-    BatchFn fn = batch_fn(o.rows_per_thread);
-    int occ = occupancy((const void *)fn, kScanBlock, 0);
-    int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
-    const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
     b->opts = o;
     b->opts.blocks_per_cu = bpc;
     const void *ptrs[5] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts};
-    const bool reuse = b->exec && grid == b->grid && b->graph_rpt == o.rows_per_thread &&
+    const bool reuse = b->exec && grid == b->grid && b->graph_rpt == o.rows_per_thread && b->graph_udf == udf &&
                        memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
     if (reuse) return ESC_OK;
     destroy_graph(b);
@@ -344,6 +370,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
     memcpy(b->graph_ptrs, ptrs, sizeof ptrs);
     b->graph_rpt = o.rows_per_thread;
+    b->graph_udf = udf;
     return ESC_OK;
 }
 
@@ -427,7 +454,7 @@ int autotune(esc_batch *b, hipStream_t s)
     int rc = ESC_OK;
     const int rpts[] = {16, 8};
     const int groups[] = {0, 16, 8};
-    const int chunks[] = {1 << 17, 1 << 19, 1 << 21};
+    const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
     for (int rpt : rpts)
         for (int grp : groups)
             for (int ch : chunks) {

@@ -399,6 +399,7 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     for (auto &c : cnf) {
         for (size_t j = 0; j < c.size(); j++) {
             const Leaf &L = C.leaves[c[j]];
+            if (L.udf) P.flags |= P_HAS_UDF;
             if (L.udf)
                 for (Insn u : L.uops) {
                     if (!(u.flags & F_CONST)) u.src = (uint8_t)slot_of[u.src];

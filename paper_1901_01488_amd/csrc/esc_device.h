@@ -152,23 +152,29 @@ __device__ __forceinline__ void run_udf(const Insn &I, const uint32_t (&v)[KK][R
 }
 
 // Runs the program on the loaded slots: returns valid & P(row) per row slot.
-template <int K, int RPT, int KK = (K > 0 ? K : 1)>
+// UDF = false is the variant for programs without udf instructions (it does
+// not reserve registers for the udf accumulator).
+template <int K, int RPT, bool UDF = true, int KK = (K > 0 ? K : 1)>
 __device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid)
 {
     uint32_t acc = valid, cm = 0;
-    uint32_t u[RPT];
+    uint32_t u[UDF ? RPT : 1];
 #pragma unroll
-    for (int r = 0; r < RPT; r++) u[r] = 0;
+    for (int r = 0; r < (UDF ? RPT : 1); r++) u[r] = 0;
     const int n = P.ninsn;
     for (int i = 0; i < n; i++) {
         const Insn I = P.insn[i];
-        if (I.op >= U_LOAD) {
-            run_udf<K, RPT>(I, v, u);
-            continue;
-        }
         uint32_t m = 0;
-        if (I.flags & F_SRC_UDF) m = run_test<RPT>(I, P.kpool, u);
-        else for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+        if constexpr (UDF) {
+            if (I.op >= U_LOAD) {
+                run_udf<K, RPT>(I, v, u);
+                continue;
+            }
+            if (I.flags & F_SRC_UDF) m = run_test<RPT>(I, P.kpool, u);
+            else for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+        } else {
+            for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+        }
         if (I.flags & F_SINGLE) {
             acc &= m;
         } else {
@@ -227,14 +233,6 @@ __device__ __forceinline__ uint32_t valid_bits(int64_t base, int64_t n)
     constexpr int TILE = kWave * RPT;
     if (base + TILE <= n) return all_rows<RPT>();
     return bits_of<RPT>([&](int r) { return row_of(base, r) < n; });
-}
-
-// Qualifying rows of a loaded tile for this lane.
-template <int K, int RPT, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ uint32_t eval_count(const Program &P, const uint32_t (&v)[KK][RPT], int64_t base,
-                                               int64_t n)
-{
-    return (uint32_t)__popc(run_program<K, RPT>(P, v, valid_bits<RPT>(base, n)));
 }
 
 // Sum of a per-lane value over the wave.

@@ -39,9 +39,9 @@ typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsig
 typedef void (*WriteFn)(const Program, const ColPtrs, int64_t, const uint32_t *, const ProjArgs, int32_t *,
                         unsigned long long);
 
-CountFn count_fn(int nslots, int variant);
-int count_rpt(int variant);
-WriteFn write_fn(int nslots, int rpt);
+CountFn count_fn(int nslots, int variant, bool udf);
+int count_rpt(int variant, int nslots);
+WriteFn write_fn(int nslots, int rpt, bool udf);
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s);
 void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s);
 

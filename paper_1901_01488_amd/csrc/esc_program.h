@@ -42,7 +42,7 @@ struct Insn {
 };
 static_assert(sizeof(Insn) == 16, "Insn is 16 bytes");
 
-enum ProgFlags : int32_t { P_ALWAYS_TRUE = 1, P_ALWAYS_FALSE = 2 };
+enum ProgFlags : int32_t { P_ALWAYS_TRUE = 1, P_ALWAYS_FALSE = 2, P_HAS_UDF = 4 };
 
 struct Program {
     int32_t ninsn;

@@ -35,10 +35,10 @@ namespace esc {
 
 // ------------------------------------------------------------------ count
 
-// Grid-stride over wave tiles.  With DB the loads of the wave's next tile are
-// in flight while the current one is evaluated (two register buffers).  When
-// tile_counts is not null, lane 0 stores each wave tile's count there.
-template <int K, int RPT, int DB>
+// Grid-stride over wave tiles.  When tile_counts is not null, lane 0 stores
+// each wave tile's count there.  UDF = false for programs without udf
+// instructions.
+template <int K, int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            WsHeader *ws, unsigned long long *out,
                                                            uint32_t *tile_counts)
@@ -50,34 +50,15 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     const int64_t step = (int64_t)gridDim.x * NW;
     const int64_t first = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
     uint32_t cnt = 0;   // per lane
-    auto account = [&](uint32_t bits, int64_t t) {
-        const uint32_t c = (uint32_t)__popc(bits);
+    for (int64_t t = first; t < ntiles; t += step) {
+        uint32_t v[KK][RPT];
+        load_vals<K, RPT>(cp, t * TILE, n, v);
+        const uint32_t c = (uint32_t)__popc(run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(t * TILE, n)));
         if (tile_counts) {
             const uint32_t w = wave_sum(c);
             if (lane_id() == 0) tile_counts[t] = w;
         }
         cnt += c;
-    };
-    if constexpr (DB) {
-        uint32_t va[KK][RPT], vb[KK][RPT];
-        int64_t t = first;
-        if (t < ntiles) load_vals<K, RPT>(cp, t * TILE, n, va);
-        while (t < ntiles) {
-            const int64_t t1 = t + step;
-            if (t1 < ntiles) load_vals<K, RPT>(cp, t1 * TILE, n, vb);
-            account(run_program<K, RPT>(P, va, valid_bits<RPT>(t * TILE, n)), t);
-            if (t1 >= ntiles) break;
-            const int64_t t2 = t1 + step;
-            if (t2 < ntiles) load_vals<K, RPT>(cp, t2 * TILE, n, va);
-            account(run_program<K, RPT>(P, vb, valid_bits<RPT>(t1 * TILE, n)), t1);
-            t = t2;
-        }
-    } else {
-        for (int64_t t = first; t < ntiles; t += step) {
-            uint32_t v[KK][RPT];
-            load_vals<K, RPT>(cp, t * TILE, n, v);
-            account(run_program<K, RPT>(P, v, valid_bits<RPT>(t * TILE, n)), t);
-        }
     }
     cnt = wave_sum(cnt);
     __shared__ uint32_t s_cnt[NW];
@@ -172,10 +153,30 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *counts, int6
 
 // ------------------------------------------------------------------ write
 
-// Re-evaluates every wave tile and writes its qualifying rows at
-// offsets[t] + rank; the rank of a row inside the tile follows row order
-// (chunk j, lane, e): lanes below (mbcnt over the wave masks) then e.
-template <int K, int RPT>
+// Stages up to 256 values of the current chunk in the wave's LDS buffer at
+// their compacted slots, then writes the first `avail` of them to dst with
+// consecutive lanes on consecutive words (coalesced).
+template <typename V>
+__device__ __forceinline__ void stage_and_flush(uint32_t *buf, uint32_t nib, const uint32_t (&slot)[4], V &&val,
+                                                uint32_t *dst, uint32_t avail)
+{
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        if ((nib >> e) & 1u) buf[slot[e]] = val(e);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t i = lane_id(); i < avail; i += kWave) dst[i] = buf[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Re-evaluates every wave tile that has qualifying rows and writes them at
+// offsets[t] onwards, in row order.  Chunk j of a wave tile (256 rows) is
+// compacted in LDS (rank of a row = lanes below, from ballot masks, then e)
+// and each output column is written as one contiguous run.
+template <int K, int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void write_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            const uint32_t *offsets, const ProjArgs pa,
                                                            int32_t *rowids, unsigned long long cap)
@@ -184,6 +185,8 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const Program P, cons
     constexpr int KK = K > 0 ? K : 1;
     constexpr int NW = kScanBlock / kWave;
     constexpr int NJ = RPT / 4;
+    __shared__ uint32_t s_buf[NW][4 * kWave];
+    uint32_t *buf = s_buf[threadIdx.x >> 6];
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
     const int lane = lane_id();
@@ -194,48 +197,44 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const Program P, cons
         const int64_t base = t * TILE;
         uint32_t v[KK][RPT];
         load_vals<K, RPT>(cp, base, n, v);
-        const uint32_t bits = run_program<K, RPT>(P, v, valid_bits<RPT>(base, n));
-        unsigned long long pos[RPT];
-        bool sel[RPT];
-        unsigned long long p = o0;
+        const uint32_t bits = run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(base, n));
+        unsigned long long p = o0;   // output position of the chunk's first qualifying row
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
-            uint64_t b[4];
-            unsigned long long q = p;
+            const uint32_t nib = (bits >> (4 * j)) & 0xfu;
+            uint32_t pre = 0, tot = 0;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                b[e] = __ballot((bits >> (4 * j + e)) & 1u);
-                q += (unsigned long long)__popcll(b[e] & lt);
+                const uint64_t b = __ballot((nib >> e) & 1u);
+                pre += (uint32_t)__popcll(b & lt);
+                tot += (uint32_t)__popcll(b);
             }
+            if (tot == 0) continue;
+            if (p >= cap) break;
+            const uint32_t avail = (uint32_t)(p + tot <= cap ? tot : cap - p);
+            uint32_t slot[4];
+            uint32_t k = pre;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
-                const bool on = (bits >> (4 * j + e)) & 1u;
-                pos[4 * j + e] = q;
-                sel[4 * j + e] = on && q < cap;
-                q += on ? 1 : 0;
-                p += (unsigned long long)__popcll(b[e]);
+                slot[e] = k;
+                k += (nib >> e) & 1u;
             }
-        }
-        if (rowids) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++)
-                if (sel[r]) rowids[pos[r]] = (int32_t)row_of(base, r);
-        }
-        for (int q = 0; q < pa.nproj; q++) {
-            uint32_t *dst = pa.dst[q];
-            const int slot = pa.slot[q];
-            if (slot >= 0) {
-                for_slot<K>(slot, [&](auto C) {
-#pragma unroll
-                    for (int r = 0; r < RPT; r++)
-                        if (sel[r]) dst[pos[r]] = v[C][r];
-                });
-            } else {
-                const uint32_t *src = pa.src[q];
-#pragma unroll
-                for (int r = 0; r < RPT; r++)
-                    if (sel[r]) dst[pos[r]] = src[row_of(base, r)];
+            if (rowids)
+                stage_and_flush(buf, nib, slot, [&](int e) { return (uint32_t)row_of(base, 4 * j + e); },
+                                (uint32_t *)rowids + p, avail);
+            for (int q = 0; q < pa.nproj; q++) {
+                uint32_t *dst = pa.dst[q] + p;
+                const int sl = pa.slot[q];
+                if (sl >= 0) {
+                    for_slot<K>(sl, [&](auto C) {
+                        stage_and_flush(buf, nib, slot, [&](int e) { return v[C][4 * j + e]; }, dst, avail);
+                    });
+                } else {
+                    const uint32_t *src = pa.src[q];
+                    stage_and_flush(buf, nib, slot, [&](int e) { return src[row_of(base, 4 * j + e)]; }, dst, avail);
+                }
             }
+            p += tot;
         }
     }
 }
@@ -248,51 +247,38 @@ __global__ void zero_kernel(unsigned long long *p, int64_t nwords)
 
 // ------------------------------------------------------------------ dispatch tables
 
-template <int RPT, int DB, int... Ks>
+template <int RPT, bool UDF, int... Ks>
 constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 {
-    CountFn t[] = {count_kernel<Ks, RPT, DB>...};
+    CountFn t[] = {count_kernel<Ks, RPT, UDF>...};
     return t[k];
 }
 
-// variant: 0 = RPT 8 double-buffered, 1 = RPT 16, 2 = RPT 16 double-buffered,
-// 3 = RPT 32, 4 = RPT 8
-CountFn count_fn(int k, int variant)
+// variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
+// up to four column slots, 16 above (32 rows of five or more columns no
+// longer fit the register file).
+int count_rpt(int variant, int k) { return variant == 0 || k > 4 ? 16 : 32; }
+
+CountFn count_fn(int k, int variant, bool udf)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (variant) {
-    case 1: return count_table_impl<16, 0>(k, S{});
-    case 2: return count_table_impl<16, 1>(k, S{});
-    case 3: return count_table_impl<32, 0>(k, S{});
-    case 4: return count_table_impl<8, 0>(k, S{});
-    default: return count_table_impl<8, 1>(k, S{});
-    }
+    if (count_rpt(variant, k) == 16)
+        return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
+    return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
 }
 
-int count_rpt(int variant)
-{
-    switch (variant) {
-    case 1: case 2: return 16;
-    case 3: return 32;
-    default: return 8;
-    }
-}
-
-template <int RPT, int... Ks>
+template <int RPT, bool UDF, int... Ks>
 constexpr WriteFn write_table_impl(int k, std::integer_sequence<int, Ks...>)
 {
-    WriteFn t[] = {write_kernel<Ks, RPT>...};
+    WriteFn t[] = {write_kernel<Ks, RPT, UDF>...};
     return t[k];
 }
 
-WriteFn write_fn(int k, int rpt)
+WriteFn write_fn(int k, int rpt, bool udf)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (rpt) {
-    case 16: return write_table_impl<16>(k, S{});
-    case 32: return write_table_impl<32>(k, S{});
-    default: return write_table_impl<8>(k, S{});
-    }
+    if (rpt == 16) return udf ? write_table_impl<16, true>(k, S{}) : write_table_impl<16, false>(k, S{});
+    return udf ? write_table_impl<32, true>(k, S{}) : write_table_impl<32, false>(k, S{});
 }
 
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s)

@@ -131,8 +131,7 @@ class Workload:
                 preds = [self.cps[q][t] for q, t in need]
                 owners = [t for _, t in need]
                 if self.batch is None:
-                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16,
-                                           chunk_rows=1 << 21)
+                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16)
                 else:
                     self.batch.update(preds, owners)
                 c = self.batch.count()
