@@ -8,9 +8,11 @@ materialization with the projection (fk1, fk2, price).  Columns are resident
 in HBM before timing starts.
 
 value = algorithmic bytes of one step / step time, in GB/s:
-  count:        k_p * N * 4                 (the k_p columns predicate p reads)
-  materialize:  k_p * N * 4 + c_p * 16      (row ids + 3 projected values written)
-                + c_p * 4 * (projected columns not read by p, gathered)
+  count:        k_p * N * 4        (the k_p columns predicate p reads)
+  materialize:  c_p * 16 + c_p * 12
+                (row ids + 3 projected values written; the 3 projected values
+                of each qualifying row read).  The predicate is not evaluated
+                again: the count left its truth values in the workspace.
 
 Prints one JSON line.
 """
@@ -129,10 +131,9 @@ def main():
 
     N = t.nrows
     step_bytes = 0
-    for p, k, c in zip(preds, ks, counts):
-        gathered = len([j for j in proj if j not in pred_columns(p)])
-        step_bytes += k * N * 4                       # count
-        step_bytes += k * N * 4 + c * 16 + c * 4 * gathered   # materialize
+    for k, c in zip(ks, counts):
+        step_bytes += k * N * 4                                  # count
+        step_bytes += c * 4 * (1 + len(proj)) + c * 4 * len(proj)   # materialize
 
     log("warmup")
     for _ in range(args.warmup):

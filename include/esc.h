@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 1
+#define ESC_ABI_VERSION 2
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -177,15 +177,17 @@ int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);
  * aligned, zero-filled before its first use (esc_workspace_init does that);
  * every successful call leaves it ready for the next call.  Calls that may
  * overlap in time (different streams) need distinct workspaces.  A workspace
- * sized for materialization (materialize = 1) also receives, from every
- * esc_count, the qualifying-row count of each tile of rows. */
+ * sized for materialization (materialize = 1; about nrows/4 bytes) also
+ * receives, from every esc_count, the qualifying-row count of each tile of
+ * rows and the per-row truth values as bit masks. */
 int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes);
 int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream);
 
 /* Exact COUNT(*) of the selection (Section 2: the selectivity sub-query
  * with a temporary COUNT aggregate).  Blocks until the count is on the
- * host.  With a materialization-sized workspace the per-tile counts are
- * left in it for a following esc_materialize of the same predicate. */
+ * host.  With a materialization-sized workspace the per-tile counts and
+ * truth masks are left in it for a following esc_materialize of the same
+ * predicate. */
 int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
               void *dev_ws, size_t ws_bytes, void *stream, uint64_t *out_count);
 
@@ -205,10 +207,11 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
  * dev_rowids may be NULL when only projections are wanted.
  * When the last scan on this workspace was an esc_count of the same table
  * handle and predicate handle (the ESC flow: count, decide, materialize),
- * its per-tile counts are reused and the columns are read once more only;
- * this assumes the table's contents did not change in between (call
- * esc_workspace_init after changing them).  Otherwise the call counts
- * first.  Needs a workspace of esc_workspace_size(t, 1, ...) bytes. */
+ * its per-tile counts and truth masks are reused and the predicate's columns
+ * are not read again, only the projected ones; this assumes the table's
+ * contents did not change in between (call esc_workspace_init after
+ * changing them).  Otherwise the call counts first.  Needs a workspace of
+ * esc_workspace_size(t, 1, ...) bytes. */
 int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                     const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
                     void *const *dev_proj_out, uint64_t capacity,
@@ -216,8 +219,8 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
 
 /* ------------------------------------------------------------------ batched
  *
- * "The same procedure is applied to each table having selection predicates"
- * (Section 2): many selectivity sub-queries at once.  One persistent kernel
+ * Section 2 runs one selectivity sub-query for every table that carries a
+ * selection; this runs many such sub-queries at once.  One persistent kernel
  * reads each table's columns once per predicate group and counts every
  * predicate of the group; the whole launch is captured in a hipGraph.
  * The batch allocates its own device memory (work list, programs, counts)
@@ -225,10 +228,12 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
 typedef struct {
     int32_t autotune;        /* 1: time candidate configurations at create */
     int32_t block;           /* threads per block (256 or 512); 0 = default */
-    int32_t rows_per_thread; /* 8 or 16; 0 = default */
+    int32_t rows_per_thread; /* lane masks: 8 or 16; wave masks: 4 or 8; other values = 8 */
     int32_t group;           /* predicates evaluated per pass over a chunk; 0 = all of the table's */
     int32_t chunk_rows;      /* rows per work item; 0 = about 8 items per block of the grid */
     int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
+    int32_t wave_masks;      /* 1: truth values as 64-bit wave masks per row slot, clause logic and
+                                counts on the scalar unit; 0: per-lane bit masks */
 } esc_batch_opts;
 
 int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,

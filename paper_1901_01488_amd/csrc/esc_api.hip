@@ -68,20 +68,24 @@ ColPtrs slot_ptrs(const esc_table *t, const Program &P, int nt)
 __global__ void store_u64_kernel(unsigned long long *dst, unsigned long long v) { *dst = v; }
 
 // Workspace of a materialization: header, per-wave-tile counts (uint32),
-// then row-order offsets (uint32, one more than there are tiles).
+// row-order offsets (uint32, one more than there are tiles), then the lane
+// masks of every wave tile (64 uint32 per tile).  Each part starts on a
+// 256-byte boundary.
 struct WsLayout {
     int64_t ntiles;
-    size_t counts_off, offsets_off, bytes;
+    size_t counts_off, offsets_off, bits_off, bytes;
 };
 
 WsLayout ws_layout(int64_t nrows, int rpt)
 {
     WsLayout L;
     const int64_t tile = 64 * (int64_t)rpt;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     L.ntiles = (nrows + tile - 1) / tile;
     L.counts_off = sizeof(WsHeader);
-    L.offsets_off = (L.counts_off + (size_t)L.ntiles * 4 + 255) & ~(size_t)255;
-    L.bytes = L.offsets_off + (size_t)(L.ntiles + 1) * 4;
+    L.offsets_off = up(L.counts_off + (size_t)L.ntiles * 4);
+    L.bits_off = up(L.offsets_off + (size_t)(L.ntiles + 1) * 4);
+    L.bytes = L.bits_off + (size_t)L.ntiles * 64 * 4;
     return L;
 }
 
@@ -208,17 +212,21 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
     } else {
         const int rpt = count_rpt(ctx->count_variant, p->prog.nslots);
         const WsLayout L = ws_layout(t->nrows, rpt);
-        uint32_t *tiles = nullptr;
-        if (ws_bytes >= L.bytes) tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
-        else if (need_tiles) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, L.bytes);
+        TileOut to{nullptr, nullptr};
+        if (ws_bytes >= L.bytes) {
+            to.counts = (uint32_t *)((char *)dev_ws + L.counts_off);
+            to.bits = (uint32_t *)((char *)dev_ws + L.bits_off);
+        } else if (need_tiles) {
+            return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, L.bytes);
+        }
         CountFn fn = count_fn(P.nslots, ctx->count_variant, (P.flags & P_HAS_UDF) != 0);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
         int64_t grid = (int64_t)ctx->num_cus * (ctx->bpc > 0 ? ctx->bpc : occ);
         const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
         if (grid > blocks_needed) grid = blocks_needed;
         hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
-                           (WsHeader *)dev_ws, dev_out, tiles);
-        if (tiles) remember_tiles(ctx, dev_ws, t, p, rpt);
+                           (WsHeader *)dev_ws, dev_out, to);
+        if (to.counts) remember_tiles(ctx, dev_ws, t, p, rpt);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ESC_OK : hip_fail(e, "count kernel launch");
@@ -267,9 +275,6 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
         const int c = proj_cols[q];
         if (c < 0 || c >= ncols) return fail(ESC_ERR_INVALID, "projected column %d out of range", c);
         if (capacity > 0 && !dev_proj_out[q]) return fail(ESC_ERR_INVALID, "projection output %d is null", q);
-        pa.slot[q] = -1;
-        for (int s = 0; s < P.nslots; s++)
-            if (P.slot_col[s] == c) pa.slot[q] = s;
         pa.src[q] = (const uint32_t *)t->cols[c];
         pa.dst[q] = capacity > 0 ? (uint32_t *)dev_proj_out[q] : nullptr;
     }
@@ -282,7 +287,8 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     WsHeader *h = (WsHeader *)dev_ws;
     uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
     uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
-    // pass 1: per-wave-tile counts, unless the preceding count left them
+    const uint32_t *bits = (const uint32_t *)((char *)dev_ws + L.bits_off);
+    // pass 1: per-wave-tile counts and lane masks, unless the preceding count left them
     if (!tiles_valid(ctx, dev_ws, t, p, rpt)) {
         if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true))) return rc;
     }
@@ -290,13 +296,13 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     launch_scan(tiles, L.ntiles, offsets, h, s);
     // pass 3: write
     if (capacity > 0) {
-        WriteFn fn = write_fn(P.nslots, rpt, (P.flags & P_HAS_UDF) != 0);
+        WriteFn fn = write_fn(rpt);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
         int64_t grid = (int64_t)ctx->num_cus * (ctx->mat_bpc > 0 ? std::min(ctx->mat_bpc, occ) : occ);
         const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
         if (grid > blocks_needed) grid = blocks_needed;
-        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
-                           offsets, pa, dev_rowids, (unsigned long long)capacity);
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, bits, offsets, t->nrows, pa, dev_rowids,
+                           (unsigned long long)capacity);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "materialize kernel launch");

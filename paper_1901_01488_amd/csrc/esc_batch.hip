@@ -2,9 +2,8 @@
 // sub-queries over several tables in one persistent kernel, launched from a
 // hipGraph.
 //
-// The paper runs one selectivity sub-query per table with a selection
-// (Section 2: "the same procedure is applied to each table having selection
-// predicates").  Here all of them run at once: the predicates of a table are
+// Section 2 runs one selectivity sub-query for every table that carries a
+// selection.  Here all of them run at once: the predicates of a table are
 // packed into groups whose column union fits the register slots; a group's
 // rows are cut into chunks, and the (group, chunk) work items sit in a list
 // ordered by decreasing cost.  Each block of the persistent grid pops items
@@ -55,14 +54,16 @@ struct BatchItem {
 };
 
 // The waves of a block walk the item's wave tiles independently; each wave
-// tile is loaded once and every predicate of the group runs on it.
-template <int K, int RPT, bool UDF>
+// tile is loaded once and every predicate of the group runs on it.  WAVE
+// selects the wave-mask evaluator (scalar clause logic and counts) over the
+// per-lane bit masks.
+template <int K, int RPT, bool UDF, bool WAVE>
 __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
                                          uint32_t (*s_cnt)[kScanBlock / 64])
 {
     constexpr int TILE = kWave * RPT;
     constexpr int NW = kScanBlock / kWave;
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     ColPtrs cp{};
     cp.nt = 1;
 #pragma unroll
@@ -71,15 +72,23 @@ __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &i
     for (int64_t base = it.r0 + (int64_t)wave * TILE; base < it.r1; base += (int64_t)NW * TILE) {
         uint32_t v[K][RPT];
         load_vals<K, RPT>(cp, base, it.r1, v);
-        const uint32_t valid = valid_bits<RPT>(base, it.r1);
-        for (int i = 0; i < npred; i++) {
-            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
-            if (lane_id() == 0) s_cnt[i][wave] += c;
+        if constexpr (WAVE) {
+            for (int i = 0; i < npred; i++) {
+                const uint32_t c = count_program_wave<K, RPT, UDF>(progs[g.pbegin + i], v, base, it.r1);
+                if (lane_id() == 0) s_cnt[i][wave] += c;
+            }
+        } else {
+            const uint32_t valid = valid_bits<RPT>(base, it.r1);
+            for (int i = 0; i < npred; i++) {
+                const uint32_t c =
+                    wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
+                if (lane_id() == 0) s_cnt[i][wave] += c;
+            }
         }
     }
 }
 
-template <int RPT, bool UDF>
+template <int RPT, bool UDF, bool WAVE>
 __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
                                                            const BatchItem *__restrict__ items,
                                                            const Program *__restrict__ progs,
@@ -94,19 +103,19 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= nitems) break;
         const BatchItem it = items[item];
         const BatchGroup &g = groups[it.group];
         switch (g.K) {
-        case 1: run_item<1, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 2: run_item<2, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 3: run_item<3, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 4: run_item<4, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 5: run_item<5, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 6: run_item<6, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 7: run_item<7, RPT, UDF>(g, it, progs, s_cnt); break;
-        default: run_item<8, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 1: run_item<1, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 2: run_item<2, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 3: run_item<3, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 4: run_item<4, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 5: run_item<5, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 6: run_item<6, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 7: run_item<7, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        default: run_item<8, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < g.npred; i += kScanBlock) {
@@ -125,10 +134,16 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
 typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
-static BatchFn batch_fn(int rpt, bool udf)
+// Lane masks: 8 or 16 rows per lane; wave masks: 4 or 8 (the masks of a
+// row slot take two scalar registers).
+static BatchFn batch_fn(int rpt, bool udf, bool wave)
 {
-    if (rpt == 16) return udf ? batch_kernel<16, true> : batch_kernel<16, false>;
-    return udf ? batch_kernel<8, true> : batch_kernel<8, false>;
+    if (wave) {
+        if (rpt == 4) return udf ? batch_kernel<4, true, true> : batch_kernel<4, false, true>;
+        return udf ? batch_kernel<8, true, true> : batch_kernel<8, false, true>;
+    }
+    if (rpt == 16) return udf ? batch_kernel<16, true, false> : batch_kernel<16, false, false>;
+    return udf ? batch_kernel<8, true, false> : batch_kernel<8, false, false>;
 }
 
 __global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
@@ -172,8 +187,7 @@ struct esc_batch {
     unsigned int *d_queue = nullptr;     // [0] next item, [1] number of items
     size_t cap_counts = 0;               // predicates the counters and the graph cover
     const void *graph_ptrs[5] = {};      // buffers the captured graph refers to
-    int graph_rpt = 0;
-    bool graph_udf = false;
+    const void *graph_fn = nullptr;      // kernel the captured graph launches
     size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
     unsigned long long *h_counts = nullptr;   // pinned
     int nitems = 0;
@@ -308,7 +322,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
 {
     bool udf = false;
     for (size_t p = 0; p < b->src.size(); p++) udf |= b->constant[p] == 0 && (b->src[p].flags & P_HAS_UDF) != 0;
-    BatchFn fn = batch_fn(o.rows_per_thread, udf);
+    BatchFn fn = batch_fn(o.rows_per_thread, udf, o.wave_masks != 0);
     const int occ = occupancy((const void *)fn, kScanBlock, 0);
     const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
     const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
@@ -351,7 +365,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     b->opts = o;
     b->opts.blocks_per_cu = bpc;
     const void *ptrs[5] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts};
-    const bool reuse = b->exec && grid == b->grid && b->graph_rpt == o.rows_per_thread && b->graph_udf == udf &&
+    const bool reuse = b->exec && grid == b->grid && b->graph_fn == (const void *)fn &&
                        memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
     if (reuse) return ESC_OK;
     destroy_graph(b);
@@ -369,8 +383,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     b->graph = g;
     if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
     memcpy(b->graph_ptrs, ptrs, sizeof ptrs);
-    b->graph_rpt = o.rows_per_thread;
-    b->graph_udf = udf;
+    b->graph_fn = (const void *)fn;
     return ESC_OK;
 }
 
@@ -416,8 +429,8 @@ void load_tune_file()
     if (!f) return;
     char key[4096];
     esc_batch_opts o{};
-    while (fscanf(f, "%4095s %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
-                  &o.blocks_per_cu) == 6)
+    while (fscanf(f, "%4095s %d %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
+                  &o.blocks_per_cu, &o.wave_masks) == 7)
         g_tune_cache[key] = o;
     fclose(f);
 }
@@ -428,7 +441,8 @@ void save_tune(const std::string &key, const esc_batch_opts &o)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows, o.blocks_per_cu);
+    fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
+            o.blocks_per_cu, o.wave_masks);
     fclose(f);
 }
 
@@ -452,15 +466,17 @@ int autotune(esc_batch *b, hipStream_t s)
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ESC_ERR_HIP, "hipEventCreate failed");
     int rc = ESC_OK;
-    const int rpts[] = {16, 8};
+    // (wave masks, rows per lane)
+    const int shapes[][2] = {{0, 16}, {0, 8}, {1, 8}, {1, 4}};
     const int groups[] = {0, 16, 8};
     const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
-    for (int rpt : rpts)
+    for (const auto &sh : shapes)
         for (int grp : groups)
             for (int ch : chunks) {
                 esc_batch_opts o{};
                 o.block = kScanBlock;
-                o.rows_per_thread = rpt;
+                o.wave_masks = sh[0];
+                o.rows_per_thread = sh[1];
                 o.group = grp;
                 o.chunk_rows = ch;
                 if ((rc = install(b, o))) goto done;
@@ -554,7 +570,12 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     }
     esc_batch_opts o{};
     if (opts) o = *opts;
-    if (o.rows_per_thread != 16) o.rows_per_thread = 8;
+    o.wave_masks = o.wave_masks != 0;
+    if (o.wave_masks) {
+        if (o.rows_per_thread != 4) o.rows_per_thread = 8;
+    } else if (o.rows_per_thread != 16) {
+        o.rows_per_thread = 8;
+    }
     o.block = kScanBlock;
     if (opts && opts->autotune) rc = autotune(b, (hipStream_t)stream);
     else rc = install(b, o);

@@ -16,13 +16,19 @@ struct ColPtrs {
     int32_t nt;   // 1: streaming (non-temporal) loads
 };
 
-// projected columns of a materialization: slot >= 0 when the column is
-// already in registers, else it is gathered from src
+// projected columns of a materialization (source column, output array)
 struct ProjArgs {
     int32_t nproj;
-    int32_t slot[ESC_MAX_PROJ];
     const uint32_t *src[ESC_MAX_PROJ];
     uint32_t *dst[ESC_MAX_PROJ];
+};
+
+// Per-wave-tile results of a count pass, kept for a materialization:
+// counts[t] = qualifying rows of wave tile t; bits[64 t + l] = lane l's
+// truth mask of tile t (bit r = row slot r).
+struct TileOut {
+    uint32_t *counts;
+    uint32_t *bits;
 };
 
 // first 64 bytes of a scan workspace; per-wave-tile counts and output offsets follow
@@ -35,13 +41,12 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) == 64, "workspace header is 64 bytes");
 
-typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsigned long long *, uint32_t *);
-typedef void (*WriteFn)(const Program, const ColPtrs, int64_t, const uint32_t *, const ProjArgs, int32_t *,
-                        unsigned long long);
+typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsigned long long *, const TileOut);
+typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjArgs, int32_t *, unsigned long long);
 
 CountFn count_fn(int nslots, int variant, bool udf);
 int count_rpt(int variant, int nslots);
-WriteFn write_fn(int nslots, int rpt, bool udf);
+WriteFn write_fn(int rpt);
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s);
 void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s);
 

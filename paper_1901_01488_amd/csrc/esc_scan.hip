@@ -9,17 +9,19 @@
 // wave-uniform control, and the qualifying rows come out as per-lane bit
 // masks.  Waves are independent; nothing per row is stored by a count.
 //
-// Materialization is order-preserving stream compaction in two data
-// passes and no inter-block waiting:
-//   1. the count pass also stores the qualifying-row count of every wave
-//      tile (the selectivity sub-query leaves this behind for free);
-//   2. one block scans those counts into row-order output offsets;
-//   3. the write pass re-evaluates each wave tile, ranks its qualifying rows
-//      with lane masks (ballot + mbcnt) and writes row ids and projected
-//      columns at offset + rank.
-// When the count pass of step 1 was the caller's own preceding esc_count on
-// the same workspace, table and predicate, materialization reuses it and
-// reads the data once more only.
+// Materialization is order-preserving stream compaction in two passes and
+// no inter-block waiting:
+//   1. the count pass (the selectivity sub-query itself) also stores, per
+//      wave tile, its qualifying-row count and every lane's truth mask
+//      (1/32 of the bytes of one 4-byte column);
+//   2. one block scans the tile counts into row-order output offsets;
+//   3. the write pass reads the masks instead of the predicate's columns,
+//      ranks the qualifying rows of each 256-row chunk with ballot masks,
+//      compacts row ids and projected values in LDS and writes them as
+//      contiguous runs at offset + rank.
+// When the count pass was the caller's own preceding esc_count on the same
+// workspace, table and predicate (count, decide, then materialize),
+// materialization never reads the predicate's columns again.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -35,34 +37,35 @@ namespace esc {
 
 // ------------------------------------------------------------------ count
 
-// Grid-stride over wave tiles.  When tile_counts is not null, lane 0 stores
-// each wave tile's count there.  UDF = false for programs without udf
-// instructions.
+// Grid-stride over wave tiles.  When to.counts is not null, every wave tile's
+// count and lane masks are stored there.  UDF = false for programs without
+// udf instructions.
 template <int K, int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
-                                                           WsHeader *ws, unsigned long long *out,
-                                                           uint32_t *tile_counts)
+                                                           WsHeader *ws, unsigned long long *out, const TileOut to)
 {
     constexpr int TILE = kWave * RPT;
     constexpr int KK = K > 0 ? K : 1;
     constexpr int NW = kScanBlock / kWave;
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
-    const int64_t first = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
+    const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
     uint32_t cnt = 0;   // per lane
     for (int64_t t = first; t < ntiles; t += step) {
         uint32_t v[KK][RPT];
         load_vals<K, RPT>(cp, t * TILE, n, v);
-        const uint32_t c = (uint32_t)__popc(run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(t * TILE, n)));
-        if (tile_counts) {
+        const uint32_t bits = run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(t * TILE, n));
+        const uint32_t c = (uint32_t)__popc(bits);
+        if (to.counts) {
             const uint32_t w = wave_sum(c);
-            if (lane_id() == 0) tile_counts[t] = w;
+            if (lane_id() == 0) to.counts[t] = w;
+            to.bits[t * kWave + lane_id()] = bits;
         }
         cnt += c;
     }
     cnt = wave_sum(cnt);
     __shared__ uint32_t s_cnt[NW];
-    const int wave = threadIdx.x >> 6;
+    const int wave = wave_id();
     if (lane_id() == 0) s_cnt[wave] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -172,32 +175,34 @@ __device__ __forceinline__ void stage_and_flush(uint32_t *buf, uint32_t nib, con
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Re-evaluates every wave tile that has qualifying rows and writes them at
-// offsets[t] onwards, in row order.  Chunk j of a wave tile (256 rows) is
-// compacted in LDS (rank of a row = lanes below, from ballot masks, then e)
-// and each output column is written as one contiguous run.
-template <int K, int RPT, bool UDF>
-__global__ __launch_bounds__(kScanBlock) void write_kernel(const Program P, const ColPtrs cp, int64_t n,
-                                                           const uint32_t *offsets, const ProjArgs pa,
-                                                           int32_t *rowids, unsigned long long cap)
+// Writes the qualifying rows of every wave tile at offsets[t] onwards, in row
+// order, from the lane masks of the count pass.  Chunk j of a wave tile (256
+// rows) is compacted in LDS (rank of a row = lanes below, from ballot masks,
+// then e) and each output column is written as one contiguous run.  A
+// projected column is read with the tile's coalesced 16-byte loads when the
+// tile is dense enough that every 64-byte line holds a qualifying row on
+// average, else gathered row by row.
+template <int RPT>
+__global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_bits, const uint32_t *offsets,
+                                                           int64_t n, const ProjArgs pa, int32_t *rowids,
+                                                           unsigned long long cap)
 {
     constexpr int TILE = kWave * RPT;
-    constexpr int KK = K > 0 ? K : 1;
     constexpr int NW = kScanBlock / kWave;
     constexpr int NJ = RPT / 4;
     __shared__ uint32_t s_buf[NW][4 * kWave];
-    uint32_t *buf = s_buf[threadIdx.x >> 6];
+    uint32_t *buf = s_buf[wave_id()];
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
     const int lane = lane_id();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int64_t t = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); t < ntiles; t += step) {
+    for (int64_t t = (int64_t)blockIdx.x * NW + wave_id(); t < ntiles; t += step) {
         const uint32_t o0 = offsets[t], o1 = offsets[t + 1];
         if (o0 == o1 || o0 >= cap) continue;   // wave-uniform
         const int64_t base = t * TILE;
-        uint32_t v[KK][RPT];
-        load_vals<K, RPT>(cp, base, n, v);
-        const uint32_t bits = run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(base, n));
+        const bool full = base + TILE <= n;
+        const bool dense = full && (o1 - o0) * 16u >= (uint32_t)TILE;
+        const uint32_t bits = tile_bits[t * kWave + lane];
         unsigned long long p = o0;   // output position of the chunk's first qualifying row
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
@@ -219,19 +224,18 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const Program P, cons
                 slot[e] = k;
                 k += (nib >> e) & 1u;
             }
+            const int64_t r0 = base + (int64_t)j * (4 * kWave) + lane * 4;   // row of e = 0
             if (rowids)
-                stage_and_flush(buf, nib, slot, [&](int e) { return (uint32_t)row_of(base, 4 * j + e); },
-                                (uint32_t *)rowids + p, avail);
+                stage_and_flush(buf, nib, slot, [&](int e) { return (uint32_t)(r0 + e); }, (uint32_t *)rowids + p,
+                                avail);
             for (int q = 0; q < pa.nproj; q++) {
+                const uint32_t *src = pa.src[q];
                 uint32_t *dst = pa.dst[q] + p;
-                const int sl = pa.slot[q];
-                if (sl >= 0) {
-                    for_slot<K>(sl, [&](auto C) {
-                        stage_and_flush(buf, nib, slot, [&](int e) { return v[C][4 * j + e]; }, dst, avail);
-                    });
+                if (dense) {
+                    const u32x4 x = __builtin_nontemporal_load((const u32x4 *)(src + r0));
+                    stage_and_flush(buf, nib, slot, [&](int e) { return x[e]; }, dst, avail);
                 } else {
-                    const uint32_t *src = pa.src[q];
-                    stage_and_flush(buf, nib, slot, [&](int e) { return src[row_of(base, 4 * j + e)]; }, dst, avail);
+                    stage_and_flush(buf, nib, slot, [&](int e) { return src[r0 + e]; }, dst, avail);
                 }
             }
             p += tot;
@@ -267,19 +271,7 @@ CountFn count_fn(int k, int variant, bool udf)
     return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
 }
 
-template <int RPT, bool UDF, int... Ks>
-constexpr WriteFn write_table_impl(int k, std::integer_sequence<int, Ks...>)
-{
-    WriteFn t[] = {write_kernel<Ks, RPT, UDF>...};
-    return t[k];
-}
-
-WriteFn write_fn(int k, int rpt, bool udf)
-{
-    using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    if (rpt == 16) return udf ? write_table_impl<16, true>(k, S{}) : write_table_impl<16, false>(k, S{});
-    return udf ? write_table_impl<32, true>(k, S{}) : write_table_impl<32, false>(k, S{});
-}
+WriteFn write_fn(int rpt) { return rpt == 16 ? write_kernel<16> : write_kernel<32>; }
 
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s)
 {

@@ -193,3 +193,49 @@ def test_constant_predicates_materialize(ctx):
         if want:
             assert torch.equal(ids.cpu(), torch.arange(t.nrows, dtype=torch.int32))
             assert torch.equal(out, dt.cols[2])
+
+
+def test_materialize_reuse_and_density_mix(ctx):
+    """The write pass reads the truth masks the count pass left in the
+    workspace.  On one workspace: materialize after the same predicate's
+    count (masks reused), after another predicate's count (must count
+    again), and twice in a row; predicates whose tiles are dense (coalesced
+    projection loads), sparse (gathers), mixed, and near the switch-over
+    density of 1 in 16.  Rows and projections against the oracle."""
+    import torch
+    n = 1_000_003
+    rng = np.random.default_rng(91)
+    cols = [np.arange(n, dtype=np.int32),
+            rng.integers(0, 4096, n).astype(np.int32),
+            rng.standard_normal(n).astype(np.float32)]
+    t = dg.Table("mix", n, [dg.INT32, dg.INT32, dg.FLOAT32], cols, ["u"] * 3, [None] * 3)
+    dt = esc.device_table(t)
+    specs = {
+        "dense_block": ("between", 0, n // 3, n // 2),
+        "sparse": ("eq", 1, 7),
+        "mixed": ("or", [("between", 0, 100_000, 180_000), ("eq", 1, 9)]),
+        "near_16th": ("lt", 1, 256),
+        "float": ("and", [("gt", 2, 0.5), ("lt", 1, 3000)]),
+    }
+    preds = {k: esc.Pred(dt, v) for k, v in specs.items()}
+    want = {k: scan.materialize(t, v, [2, 1, 0]) for k, v in specs.items()}
+    ws = ctx.workspace(dt, True, key="reuse-test")   # the same workspace throughout
+    ids = torch.empty(n, dtype=torch.int32, device="cuda")
+    outs = [torch.empty(n, dtype=dt.cols[j].dtype, device="cuda") for j in (2, 1, 0)]
+
+    def mat(k):
+        c = ctx.materialize(dt, preds[k], [2, 1, 0], ids, outs, n, ws=ws)
+        wc, wids, wouts = want[k]
+        assert c == wc, k
+        assert_same_rows(ids[:c].cpu().numpy(), [o[:c].cpu().numpy() for o in outs], wids, wouts)
+
+    order = ["dense_block", "sparse", "mixed", "near_16th", "float"]
+    for k in order:                       # count, then materialize with the masks it left
+        assert ctx.count(dt, preds[k], ws=ws) == want[k][0]
+        mat(k)
+    assert ctx.count(dt, preds["sparse"], ws=ws) == want["sparse"][0]
+    mat("dense_block")                    # masks belong to another predicate: counts again
+    mat("mixed")
+    mat("mixed")                          # twice in a row
+    for k in reversed(order):             # materialize without a preceding count
+        mat(k)
