@@ -286,9 +286,6 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=300):
             "plain_1M_materialize_us_p99": round(float(np.percentile(tm, 99)), 1)}
 
 
-if __name__ == "__main__":
-    main()
-
 
 def copy_reference():
     """A plain 1 GiB device-to-device copy, for calibrating HBM byte counters."""
@@ -305,7 +302,8 @@ def copy_reference():
 def learned_workload(args):
     """Learned gate on a 100M x 6 correlated / skewed table: exact labels by
     the batched scan, GPU training, q-error on held-out batches of 4,096,
-    routing and exact fallback."""
+    routing and exact fallback.  Predicates are conjunctions built around
+    sampled rows (every one selects at least one row)."""
     import torch
     from paper_1901_01488_amd import datagen as dg
     from paper_1901_01488_amd import esc, learned
@@ -322,7 +320,7 @@ def learned_workload(args):
     ntrain, nval, ntest = args.train_preds, 8192, 4096
     log("learned: predicates")
     t0 = time.perf_counter()
-    specs = dg.preds_mixed(t, ntrain + nval + ntest, seed=dg.pred_seed(3))
+    specs = dg.preds_anchored(t, ntrain + nval + ntest, seed=dg.pred_seed(3))
     cps = [esc.Pred(dt, p) for p in specs]
     gen_s = time.perf_counter() - t0
     log("learned: labels")
@@ -335,7 +333,8 @@ def learned_workload(args):
     y = learned.labels(counts, n)
     tr, va, te = slice(0, ntrain), slice(ntrain, ntrain + nval), slice(ntrain + nval, None)
     est = learned.Estimator(ctx, dt, cmin, cmax, dg.mlp_init(dg.MLP_SEED))
-    loss, train_s = est.train(x[tr], y[tr], epochs=30, batch=1024, lr=1e-3, order_seed=dg.MLP_SEED)
+    phases = [(20, 1e-3), (10, 2e-4), (10, 4e-5)]
+    loss, train_s = est.fit(x[tr], y[tr], phases, batch=256, order_seed=dg.MLP_SEED)
     beta = learned.validation_beta(est.predict(x[va]), counts[va], n)
     xt = torch.from_numpy(x[te]).to(dev)
     out = torch.empty(ntest, dtype=torch.float32, device=dev)
@@ -356,13 +355,18 @@ def learned_workload(args):
     exact = learned.exact_counts(ctx, dt, [cps[i] for i in idx]) if len(idx) else np.zeros(0, np.uint64)
     host = t.host()
     rng = np.random.default_rng(0)
-    check = [int(i) for i in rng.choice(len(counts), 300, replace=False)] + [int(i) for i in idx[:100]]
-    oracle_errors = sum(int(counts[i]) != scan.count(host, specs[i]) for i in check)
+    check = [int(i) for i in rng.choice(len(counts), 40, replace=False)] + [int(i) for i in idx[:20]]
+    oracle_errors = 0
+    for j, i in enumerate(check):
+        oracle_errors += int(counts[i]) != scan.count(host, specs[i])
+        if j % 10 == 9:
+            log(f"learned: oracle check {j + 1}/{len(check)}")
     flops = 4096 * 2 * (64 * 256 + 2 * 256 * 256 + 256)
     print(json.dumps({
         "workload": "learned gate: 100M x 6 table, %d training predicates, held-out batch of 4096" % ntrain,
         "label_s": round(label_s, 2), "label_row_predicates_per_s": round(len(cps) * n / label_s, 1),
-        "train_s": round(train_s, 2), "epochs": 30, "final_loss": float(np.mean(loss[-50:])),
+        "train_s": round(train_s, 2), "schedule": "batch 256; epochs@lr " + ", ".join(f"{e}@{l:g}" for e, l in phases),
+        "final_loss": float(np.mean(loss[-50:])), "zero_count_fraction": float((counts == 0).mean()),
         "inference_us_per_4096": round(infer_us, 1), "inference_tflops": round(flops / (infer_us * 1e-6) / 1e12, 3),
         "qerror_median": float(np.median(q)), "qerror_p90": float(np.quantile(q, 0.9)),
         "qerror_p99": float(np.quantile(q, 0.99)), "qerror_max": float(q.max()), "beta": beta,
@@ -428,3 +432,7 @@ def planning_workload(args):
         "routed_count_errors": int((gated["counts"][r] != plain["counts"][r]).sum()),
         "batched_count_errors": int((batched["counts"] != plain["counts"]).sum()),
         "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,7 +186,8 @@ struct esc_batch {
     unsigned long long *d_counts = nullptr;
     unsigned int *d_queue = nullptr;     // [0] next item, [1] number of items
     size_t cap_counts = 0;               // predicates the counters and the graph cover
-    const void *graph_ptrs[5] = {};      // buffers the captured graph refers to
+    const void *graph_ptrs[6] = {};      // buffers the captured graph refers to
+    size_t graph_cap = 0;                // counters the captured graph zeroes and copies
     const void *graph_fn = nullptr;      // kernel the captured graph launches
     size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
     unsigned long long *h_counts = nullptr;   // pinned
@@ -364,9 +365,12 @@ int install(esc_batch *b, const esc_batch_opts &o)
     b->nitems = (int)nitems;
     b->opts = o;
     b->opts.blocks_per_cu = bpc;
-    const void *ptrs[5] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts};
+    // the graph bakes in these buffers, the counter capacity (zeroed and copied
+    // back) and the kernel; a buffer that was reallocated may come back at the
+    // same address with another size, so the capacity is compared too
+    const void *ptrs[6] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts, b->h_counts};
     const bool reuse = b->exec && grid == b->grid && b->graph_fn == (const void *)fn &&
-                       memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
+                       b->graph_cap == b->cap_counts && memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
     if (reuse) return ESC_OK;
     destroy_graph(b);
     b->grid = grid;
@@ -384,6 +388,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
     memcpy(b->graph_ptrs, ptrs, sizeof ptrs);
     b->graph_fn = (const void *)fn;
+    b->graph_cap = b->cap_counts;
     return ESC_OK;
 }
 

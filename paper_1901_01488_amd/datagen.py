@@ -462,6 +462,65 @@ def preds_mixed(table: Table, count, seed, min_conj=1, max_conj=6, p_or=0.3):
     return out
 
 
+def _leaf_around(table, c, v, rng):
+    """A leaf on column c that row value v satisfies; widths log-uniform so
+    that selectivities spread over decades."""
+    kind = table.kinds[c]
+    frac = 10.0 ** rng.uniform(-5, 0)
+    if kind == "lognormal":
+        v = np.float32(v)
+        op = rng.choice(["lt", "gt", "between"])
+        up = np.float32(v * (1.0 + frac * 20.0) + 1e-3)
+        dn = np.float32(max(0.0, v * (1.0 - frac) - 1e-3))
+        up = up if up > v else np.nextafter(v, np.float32(np.inf))
+        dn = dn if dn < v else np.nextafter(v, np.float32(-np.inf))
+        if op == "lt":
+            return ("lt", c, up)
+        if op == "gt":
+            return ("gt", c, dn)
+        return ("between", c, dn, up)
+    v = int(v)
+    lo, hi = table.domain[c]
+    w = max(1, int(frac * (hi - lo + 1)))
+    op = rng.choice(["eq", "lt", "gt", "between", "between", "in"] if kind != "perm" else ["lt", "gt", "between"])
+    if op == "eq":
+        return ("eq", c, v)
+    if op == "lt":
+        return ("lt", c, v + 1 + int(rng.integers(0, w)))
+    if op == "gt":
+        return ("gt", c, v - 1 - int(rng.integers(0, w)))
+    if op == "between":
+        a = int(rng.integers(0, w))
+        return ("between", c, v - a, v + (w - a))
+    m = int(rng.integers(2, 17))
+    vals = [v] + [int(x) for x in rng.integers(lo, hi + 1, m - 1)]
+    rng.shuffle(vals)
+    return ("in", c, vals)
+
+
+def preds_anchored(table: Table, count, seed, min_conj=1, max_conj=4, p_or=0.2):
+    """Conjunctions built around a sampled row: every conjunct holds for
+    that row (an OR pairs a leaf it satisfies with a random leaf), so each
+    predicate selects at least one row; conjuncts are on distinct columns."""
+    rng = np.random.default_rng(seed)
+    n, ncols = table.nrows, len(table.cols)
+    rows = rng.integers(0, max(n, 1), count)
+    vals = [np.asarray(_row_values(col, rows)) for col in table.cols]
+    out = []
+    for i in range(count):
+        k = int(rng.integers(min_conj, min(max_conj, ncols) + 1))
+        cols = [int(c) for c in rng.choice(ncols, k, replace=False)]
+        conj = []
+        for c in cols:
+            leaf = _leaf_around(table, c, vals[c][i], rng)
+            if rng.random() < p_or:
+                other = int(rng.integers(0, ncols))
+                leaf = ("or", [leaf, _leaf_mixed(table, other, rng)])
+            conj.append(leaf)
+        out.append(("and", conj) if len(conj) > 1 else conj[0])
+    return out
+
+
 def preds_batched(tables, per_table=32, seed=None):
     """32 predicates per table (256 over the eight tables); returns
     (predicates, table index of each)."""

@@ -29,7 +29,7 @@ def exact_counts(ctx, table: esc.Table, preds, group=1024):
     step = 16384
     for i in range(0, len(preds), step):
         chunk = preds[i:i + step]
-        b = esc.Batch(ctx, [table], chunk, [0] * len(chunk), group=group, chunk_rows=1 << 22)
+        b = esc.Batch(ctx, [table], chunk, [0] * len(chunk), group=group)
         out[i:i + len(chunk)] = b.count()
         del b
     return out
@@ -74,6 +74,17 @@ class Estimator:
         t0 = time.perf_counter()
         loss = self.mlp.train(xt, yt, ot, len(order) // batch, batch, lr=lr)
         return loss, time.perf_counter() - t0
+
+    def fit(self, x, y, phases, batch, order_seed):
+        """Training in phases of (epochs, learning rate), Adam state carried
+        over (a step-wise decaying schedule); returns (loss of the last
+        phase, seconds)."""
+        total = 0.0
+        loss = None
+        for i, (epochs, lr) in enumerate(phases):
+            loss, s = self.train(x, y, epochs=epochs, batch=batch, lr=lr, order_seed=order_seed + i)
+            total += s
+        return loss, total
 
     def predict(self, x):
         import torch

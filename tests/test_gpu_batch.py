@@ -111,3 +111,19 @@ def test_batched_update_changes_shape(ctx, small_batch):
         b.update([cps[i] for i in pick], [owner[i] for i in pick])
         want = [scan.count(tabs[owner[i]], preds[i]) for i in pick]
         assert b.count().tolist() == want, size
+
+
+def test_batched_update_growing_counters(ctx, small_batch):
+    """Each step needs more counters than the last (the counter buffers are
+    reallocated every time, possibly at the same address with a larger size):
+    the launch graph must zero and copy back all of them."""
+    tabs, preds, owner = small_batch
+    dts = [esc.device_table(t) for t in tabs]
+    cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    want_all = [scan.count(tabs[o], p) for p, o in zip(preds, owner)]
+    b = esc.Batch(ctx, dts, cps[:1], owner[:1])
+    rng = np.random.default_rng(22)
+    for size in (2, 3, 5, 8, 12, 18, 27, 41, 62, 93, 140, 210, 256, 256, 100, 256):
+        pick = rng.choice(len(preds), size, replace=False)
+        b.update([cps[i] for i in pick], [owner[i] for i in pick])
+        assert b.count().tolist() == [want_all[i] for i in pick], size
