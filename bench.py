@@ -54,6 +54,30 @@ def pred_columns(spec):
     return cols
 
 
+def counter_traffic():
+    """HBM bytes per count-kernel launch measured with the FETCH_SIZE and
+    WRITE_SIZE counters (profiles/count_kernel_star60M_pmc.txt), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "count_kernel_star60M_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in kv.get("kernel_sources", "").split():
+        fp = os.path.join(ROOT, src)
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if h.hexdigest() != kv.get("kernel_sources_sha256"):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(t_host, preds, budget_s=25.0):
     """The oracle (single thread) on the first rows of the same table, all 32
     predicates, count only; scaled to GB/s of algorithmic bytes."""
@@ -169,7 +193,7 @@ def main():
     achieved = sum(kern_bytes) / (sum(kern_ms) / 1e3) / 1e9
     assert dcount.cpu().tolist() == counts
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(),
                 "kernel": "count_kernel (all instantiations)",
                 "avg_launch_us": round(sum(kern_ms) / len(kern_ms) * 1e3, 2),
                 "bytes_per_launch": int(sum(kern_bytes) / len(kern_bytes))}
