@@ -148,7 +148,7 @@ int esc_ctx_create(int device, esc_ctx **out)
         return hip_fail(e, "hipHostMalloc");
     }
     const char *r = getenv("ESC_COUNT_VARIANT");
-    if (r && (atoi(r) == 0 || atoi(r) == 1)) c->count_variant = atoi(r);
+    if (r && atoi(r) >= 0 && atoi(r) <= 2) c->count_variant = atoi(r);
     r = getenv("ESC_NONTEMPORAL");
     if (r) c->nt = atoi(r) != 0;
     r = getenv("ESC_BLOCKS_PER_CU");
@@ -179,7 +179,7 @@ int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
 {
     if (!t || !bytes) return fail(ESC_ERR_INVALID, "null argument");
     size_t need = sizeof(WsHeader);
-    if (materialize) need = ws_layout(t->nrows, 16).bytes;   // the smallest wave tile needs the most slots
+    if (materialize) need = ws_layout(t->nrows, 8).bytes;   // the smallest wave tile needs the most slots
     *bytes = (need + 255) & ~(size_t)255;
     return ESC_OK;
 }

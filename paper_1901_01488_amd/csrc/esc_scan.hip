@@ -260,18 +260,27 @@ constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 
 // variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
 // up to four column slots, 16 above (32 rows of five or more columns no
-// longer fit the register file).
-int count_rpt(int variant, int k) { return variant == 0 || k > 4 ? 16 : 32; }
+// longer fit the register file); variant 2: 8 rows per lane.
+int count_rpt(int variant, int k)
+{
+    if (variant == 2) return 8;
+    return variant == 0 || k > 4 ? 16 : 32;
+}
 
 CountFn count_fn(int k, int variant, bool udf)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    if (count_rpt(variant, k) == 16)
-        return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
-    return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
+    switch (count_rpt(variant, k)) {
+    case 8: return udf ? count_table_impl<8, true>(k, S{}) : count_table_impl<8, false>(k, S{});
+    case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
+    default: return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
+    }
 }
 
-WriteFn write_fn(int rpt) { return rpt == 16 ? write_kernel<16> : write_kernel<32>; }
+WriteFn write_fn(int rpt)
+{
+    return rpt == 8 ? write_kernel<8> : rpt == 16 ? write_kernel<16> : write_kernel<32>;
+}
 
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s)
 {
