@@ -228,12 +228,10 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
 typedef struct {
     int32_t autotune;        /* 1: time candidate configurations at create */
     int32_t block;           /* threads per block (256 or 512); 0 = default */
-    int32_t rows_per_thread; /* lane masks: 8 or 16; wave masks: 4 or 8; other values = 8 */
+    int32_t rows_per_thread; /* 8 or 16; other values = 8 */
     int32_t group;           /* predicates evaluated per pass over a chunk; 0 = all of the table's */
     int32_t chunk_rows;      /* rows per work item; 0 = about 8 items per block of the grid */
     int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
-    int32_t wave_masks;      /* 1: truth values as 64-bit wave masks per row slot, clause logic and
-                                counts on the scalar unit; 0: per-lane bit masks */
 } esc_batch_opts;
 
 int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,

@@ -54,10 +54,8 @@ struct BatchItem {
 };
 
 // The waves of a block walk the item's wave tiles independently; each wave
-// tile is loaded once and every predicate of the group runs on it.  WAVE
-// selects the wave-mask evaluator (scalar clause logic and counts) over the
-// per-lane bit masks.
-template <int K, int RPT, bool UDF, bool WAVE>
+// tile is loaded once and every predicate of the group runs on it.
+template <int K, int RPT, bool UDF>
 __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
                                          uint32_t (*s_cnt)[kScanBlock / 64])
 {
@@ -72,23 +70,15 @@ __device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &i
     for (int64_t base = it.r0 + (int64_t)wave * TILE; base < it.r1; base += (int64_t)NW * TILE) {
         uint32_t v[K][RPT];
         load_vals<K, RPT>(cp, base, it.r1, v);
-        if constexpr (WAVE) {
-            for (int i = 0; i < npred; i++) {
-                const uint32_t c = count_program_wave<K, RPT, UDF>(progs[g.pbegin + i], v, base, it.r1);
-                if (lane_id() == 0) s_cnt[i][wave] += c;
-            }
-        } else {
-            const uint32_t valid = valid_bits<RPT>(base, it.r1);
-            for (int i = 0; i < npred; i++) {
-                const uint32_t c =
-                    wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
-                if (lane_id() == 0) s_cnt[i][wave] += c;
-            }
+        const uint32_t valid = valid_bits<RPT>(base, it.r1);
+        for (int i = 0; i < npred; i++) {
+            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
+            if (lane_id() == 0) s_cnt[i][wave] += c;
         }
     }
 }
 
-template <int RPT, bool UDF, bool WAVE>
+template <int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
                                                            const BatchItem *__restrict__ items,
                                                            const Program *__restrict__ progs,
@@ -108,14 +98,14 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
         const BatchItem it = items[item];
         const BatchGroup &g = groups[it.group];
         switch (g.K) {
-        case 1: run_item<1, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 2: run_item<2, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 3: run_item<3, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 4: run_item<4, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 5: run_item<5, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 6: run_item<6, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        case 7: run_item<7, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
-        default: run_item<8, RPT, UDF, WAVE>(g, it, progs, s_cnt); break;
+        case 1: run_item<1, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 2: run_item<2, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 3: run_item<3, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 4: run_item<4, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 5: run_item<5, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 6: run_item<6, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 7: run_item<7, RPT, UDF>(g, it, progs, s_cnt); break;
+        default: run_item<8, RPT, UDF>(g, it, progs, s_cnt); break;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < g.npred; i += kScanBlock) {
@@ -134,16 +124,10 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
 typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
-// Lane masks: 8 or 16 rows per lane; wave masks: 4 or 8 (the masks of a
-// row slot take two scalar registers).
-static BatchFn batch_fn(int rpt, bool udf, bool wave)
+static BatchFn batch_fn(int rpt, bool udf)
 {
-    if (wave) {
-        if (rpt == 4) return udf ? batch_kernel<4, true, true> : batch_kernel<4, false, true>;
-        return udf ? batch_kernel<8, true, true> : batch_kernel<8, false, true>;
-    }
-    if (rpt == 16) return udf ? batch_kernel<16, true, false> : batch_kernel<16, false, false>;
-    return udf ? batch_kernel<8, true, false> : batch_kernel<8, false, false>;
+    if (rpt == 16) return udf ? batch_kernel<16, true> : batch_kernel<16, false>;
+    return udf ? batch_kernel<8, true> : batch_kernel<8, false>;
 }
 
 __global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
@@ -323,7 +307,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
 {
     bool udf = false;
     for (size_t p = 0; p < b->src.size(); p++) udf |= b->constant[p] == 0 && (b->src[p].flags & P_HAS_UDF) != 0;
-    BatchFn fn = batch_fn(o.rows_per_thread, udf, o.wave_masks != 0);
+    BatchFn fn = batch_fn(o.rows_per_thread, udf);
     const int occ = occupancy((const void *)fn, kScanBlock, 0);
     const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
     const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
@@ -434,8 +418,8 @@ void load_tune_file()
     if (!f) return;
     char key[4096];
     esc_batch_opts o{};
-    while (fscanf(f, "%4095s %d %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
-                  &o.blocks_per_cu, &o.wave_masks) == 7)
+    while (fscanf(f, "%4095s %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
+                  &o.blocks_per_cu) == 6)
         g_tune_cache[key] = o;
     fclose(f);
 }
@@ -446,8 +430,8 @@ void save_tune(const std::string &key, const esc_batch_opts &o)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
-            o.blocks_per_cu, o.wave_masks);
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
+            o.blocks_per_cu);
     fclose(f);
 }
 
@@ -471,17 +455,15 @@ int autotune(esc_batch *b, hipStream_t s)
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ESC_ERR_HIP, "hipEventCreate failed");
     int rc = ESC_OK;
-    // (wave masks, rows per lane)
-    const int shapes[][2] = {{0, 16}, {0, 8}, {1, 8}, {1, 4}};
+    const int rpts[] = {16, 8};
     const int groups[] = {0, 16, 8};
     const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
-    for (const auto &sh : shapes)
+    for (int rpt : rpts)
         for (int grp : groups)
             for (int ch : chunks) {
                 esc_batch_opts o{};
                 o.block = kScanBlock;
-                o.wave_masks = sh[0];
-                o.rows_per_thread = sh[1];
+                o.rows_per_thread = rpt;
                 o.group = grp;
                 o.chunk_rows = ch;
                 if ((rc = install(b, o))) goto done;
@@ -575,12 +557,7 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     }
     esc_batch_opts o{};
     if (opts) o = *opts;
-    o.wave_masks = o.wave_masks != 0;
-    if (o.wave_masks) {
-        if (o.rows_per_thread != 4) o.rows_per_thread = 8;
-    } else if (o.rows_per_thread != 16) {
-        o.rows_per_thread = 8;
-    }
+    if (o.rows_per_thread != 16) o.rows_per_thread = 8;
     o.block = kScanBlock;
     if (opts && opts->autotune) rc = autotune(b, (hipStream_t)stream);
     else rc = install(b, o);

@@ -255,98 +255,6 @@ __device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t
     return acc;
 }
 
-// ------------------------------------------------------------------
-// Wave-mask evaluation (batched scan).  Bit l of mask r is the value of row
-// slot r of lane l: a compare goes straight into a scalar register pair and
-// the clause logic runs on the scalar unit, so a range test costs two vector
-// ops per row slot and the count is a scalar popcount (no cross-lane sum).
-// The masks live in scalar registers, which bounds RPT.
-
-// Combines a test's wave masks into the result (AND) or the open clause (OR).
-template <bool AND, int RPT>
-__device__ __forceinline__ void put_wave(uint64_t (&acc)[RPT], uint64_t (&cm)[RPT], int r, uint64_t t)
-{
-    if constexpr (AND) acc[r] &= t;
-    else cm[r] |= t;
-}
-
-template <bool AND, int RPT>
-__device__ __forceinline__ void wave_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT],
-                                          uint64_t (&acc)[RPT], uint64_t (&cm)[RPT])
-{
-    switch (I.op) {
-    case T_RANGE_I32: {
-        const uint32_t lo = (uint32_t)I.a, span = (uint32_t)I.b;
-#pragma unroll
-        for (int r = 0; r < RPT; r++) put_wave<AND>(acc, cm, r, __ballot(x[r] - lo <= span));
-        break;
-    }
-    case T_RANGE_F32: {
-        const float lo = as_f((uint32_t)I.a), hi = as_f((uint32_t)I.b);
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-            const float f = as_f(x[r]);
-            put_wave<AND>(acc, cm, r, __ballot(lo <= f && f <= hi));
-        }
-        break;
-    }
-    case T_BITSET: {
-        const uint32_t lo = (uint32_t)I.a;
-        const uint64_t bits = (uint64_t)(uint32_t)I.b | ((uint64_t)(uint32_t)I.c << 32);
-#pragma unroll
-        for (int r = 0; r < RPT; r++) {
-            const uint32_t d = x[r] - lo;
-            put_wave<AND>(acc, cm, r, __ballot(d < 64u && ((bits >> (d & 63u)) & 1ull)));
-        }
-        break;
-    }
-    case T_IN_I32:
-    case T_IN_F32: {
-        // the hits accumulate in the clause masks: in AND mode no clause is
-        // open (a single-test clause), so they are free and get cleared again
-        const bool fl = I.op == T_IN_F32;
-        for (int k = 0; k < I.b; k++) {
-            const uint32_t kv = kpool[I.a + k];
-            if (fl) {
-#pragma unroll
-                for (int r = 0; r < RPT; r++) cm[r] |= __ballot(as_f(x[r]) == as_f(kv));
-            } else {
-#pragma unroll
-                for (int r = 0; r < RPT; r++) cm[r] |= __ballot(x[r] == kv);
-            }
-        }
-        if constexpr (AND) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) {
-                acc[r] &= cm[r];
-                cm[r] = 0;
-            }
-        }
-        break;
-    }
-    default:
-        if constexpr (AND) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) acc[r] = 0;
-        }
-        break;
-    }
-}
-
-template <int RPT>
-__device__ __forceinline__ void wave_apply(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT],
-                                           uint64_t (&acc)[RPT], uint64_t (&cm)[RPT])
-{
-    if (I.flags & F_SINGLE) wave_test<true, RPT>(I, kpool, x, acc, cm);
-    else wave_test<false, RPT>(I, kpool, x, acc, cm);
-}
-
-// Count of the rows of the wave tile at `base` (rows >= n excluded) that
-// satisfy the program, as a wave-uniform value.
-template <int K, int RPT, bool UDF, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ uint32_t count_program_wave(const Program &P, const uint32_t (&v)[KK][RPT],
-                                                       int64_t base, int64_t n);
-
 constexpr int kWave = 64;
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -359,49 +267,6 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 __device__ __forceinline__ int64_t row_of(int64_t base, int r)
 {
     return base + (int64_t)(r >> 2) * (4 * kWave) + lane_id() * 4 + (r & 3);
-}
-
-template <int K, int RPT, bool UDF, int KK>
-__device__ __forceinline__ uint32_t count_program_wave(const Program &P, const uint32_t (&v)[KK][RPT],
-                                                       int64_t base, int64_t n)
-{
-    uint64_t acc[RPT], cm[RPT];
-    const bool full = base + (int64_t)kWave * RPT <= n;
-#pragma unroll
-    for (int r = 0; r < RPT; r++) {
-        acc[r] = full ? ~0ull : __ballot(row_of(base, r) < n);
-        cm[r] = 0;
-    }
-    uint32_t u[UDF ? RPT : 1];
-#pragma unroll
-    for (int r = 0; r < (UDF ? RPT : 1); r++) u[r] = 0;
-    const int ni = P.ninsn;
-    for (int i = 0; i < ni; i++) {
-        const Insn I = P.insn[i];
-        bool done = false;
-        if constexpr (UDF) {
-            if (I.op >= U_LOAD) {
-                run_udf<K, RPT>(I, v, u);
-                continue;
-            }
-            if (I.flags & F_SRC_UDF) {
-                wave_apply<RPT>(I, P.kpool, u, acc, cm);
-                done = true;
-            }
-        }
-        if (!done) for_slot<K>(I.src, [&](auto C) { wave_apply<RPT>(I, P.kpool, v[C], acc, cm); });
-        if ((I.flags & (F_SINGLE | F_END_CLAUSE)) == F_END_CLAUSE) {
-#pragma unroll
-            for (int r = 0; r < RPT; r++) {
-                acc[r] &= cm[r];
-                cm[r] = 0;
-            }
-        }
-    }
-    uint32_t c = 0;
-#pragma unroll
-    for (int r = 0; r < RPT; r++) c += (uint32_t)__popcll(acc[r]);
-    return c;
 }
 
 // Loads the K slot columns of the wave tile starting at row `base`; rows at

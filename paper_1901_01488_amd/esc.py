@@ -63,8 +63,7 @@ class PredInfo(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("wave_masks", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
 _lib = None
@@ -344,15 +343,14 @@ class Batch:
     launch of a persistent kernel)."""
 
     def __init__(self, ctx: Context, tables, preds, owner, autotune=False, rows_per_thread=0, group=0,
-                 chunk_rows=0, blocks_per_cu=0, wave_masks=0, stream=None):
+                 chunk_rows=0, blocks_per_cu=0, stream=None):
         self.ctx = ctx
         self.tables = list(tables)
         self.preds = list(preds)
         self.owner = np.asarray(owner, np.int32)
         th = (ctypes.c_void_p * len(self.tables))(*[t.h for t in self.tables])
         ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
-        o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu,
-                      1 if wave_masks else 0)
+        o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu)
         h = ctypes.c_void_p()
         check(lib().esc_batch_create(ctx.h, th, len(self.tables), ph, self.owner.ctypes.data, len(self.preds),
                                      ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
@@ -374,8 +372,8 @@ class Batch:
     def opts(self):
         o = BatchOpts()
         check(lib().esc_batch_get_opts(self.h, ctypes.byref(o)))
-        return {"wave_masks": o.wave_masks, "rows_per_thread": o.rows_per_thread, "group": o.group,
-                "chunk_rows": o.chunk_rows, "blocks_per_cu": o.blocks_per_cu}
+        return {"rows_per_thread": o.rows_per_thread, "group": o.group, "chunk_rows": o.chunk_rows,
+                "blocks_per_cu": o.blocks_per_cu}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
