@@ -110,11 +110,14 @@ def main():
     ap.add_argument("--learned", action="store_true", help="learned-gate workload (100M x 6, 200K labels)")
     ap.add_argument("--planning", action="store_true", help="planning workload (1,000 three-table queries)")
     ap.add_argument("--copy-ref", action="store_true", help="1 GiB device copy (counter calibration)")
+    ap.add_argument("--batched", action="store_true", help="batched workload only (256 sub-queries, 8 tables)")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
     if args.copy_ref:
         return copy_reference()
+    if args.batched:
+        return batched_workload()
     if args.learned:
         return learned_workload(args)
     if args.planning:
@@ -327,6 +330,18 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=300):
             "plain_1M_materialize_us_p50": round(float(np.percentile(tm, 50)), 1),
             "plain_1M_materialize_us_p99": round(float(np.percentile(tm, 99)), 1)}
 
+
+
+def batched_workload():
+    """The batched workload alone: one JSON line."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc
+    torch.cuda.init()
+    ctx = esc.Context(0)
+    r = batched_vs_plain(ctx, esc, dg, torch, "cuda:0")
+    r["workload"] = "batched: 256 sub-queries over 8 tables of 10K..200M rows (376M rows), count only"
+    print(json.dumps(r), flush=True)
 
 
 def copy_reference():
