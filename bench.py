@@ -78,6 +78,52 @@ def counter_traffic():
     return int(kv["traffic_bytes_per_launch"])
 
 
+_ORACLE_TABLE = None
+
+
+def _oracle_init(meta):
+    global _ORACLE_TABLE
+    from paper_1901_01488_amd import datagen as dg
+    name, nrows, dtypes, paths, kinds, domain = meta
+    cols = [np.load(p, mmap_mode="r") for p in paths]
+    _ORACLE_TABLE = dg.Table(name, nrows, dtypes, cols, kinds, domain)
+
+
+def _oracle_one(job):
+    from oracle import scan
+    i, spec = job
+    return i, scan.count(_ORACLE_TABLE, spec)
+
+
+def oracle_counts(host, specs, idx, what):
+    """Oracle counts of specs[i] for i in idx: one single-threaded oracle per
+    worker process.  The workers are fresh interpreters (no GPU state) that
+    map the host table's columns from files written once."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    d = tempfile.mkdtemp(prefix="esc_oracle_")
+    try:
+        paths = []
+        for j, c in enumerate(host.cols):
+            pth = os.path.join(d, f"c{j}.npy")
+            np.save(pth, np.ascontiguousarray(c))
+            paths.append(pth)
+        meta = (host.name, host.nrows, list(host.dtypes), paths, list(host.kinds), list(host.domain))
+        workers = max(1, min(16, os.cpu_count() or 1, len(idx)))
+        out = {}
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(workers, initializer=_oracle_init, initargs=(meta,)) as pool:
+            jobs = [(int(i), specs[i]) for i in idx]
+            for j, (i, c) in enumerate(pool.imap_unordered(_oracle_one, jobs, chunksize=1)):
+                out[i] = c
+                if (j + 1) % max(1, len(idx) // 10) == 0:
+                    log(f"{what}: oracle {j + 1}/{len(idx)}")
+        return out, workers, time.perf_counter() - t0
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+
+
 def cpu_baseline(t_host, preds, budget_s=25.0):
     """The oracle (single thread) on the first rows of the same table, all 32
     predicates, count only; scaled to GB/s of algorithmic bytes."""
@@ -246,7 +292,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batched_vs_plain(ctx, esc, dg, torch, dev, reps=10):
+def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
     """256 selectivity sub-queries over 8 tables of 10K..200M rows: one
     autotuned graph launch of the batched kernel vs 256 plain count calls
     (each synchronous, and all queued then one synchronisation)."""
@@ -303,7 +349,7 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=10):
             "batched_opts": b.opts(), "autotune_s": round(tune_s, 2)}
 
 
-def plain_latency(ctx, esc, dg, torch, dev, reps=300):
+def plain_latency(ctx, esc, dg, torch, dev, reps=1000):
     """The Section 1 selection on a 1M-row table: wall latency of esc_count
     and esc_materialize (launch to result on the host), p50/p99."""
     t = dg.table_plain(1_000_000)
@@ -325,7 +371,13 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=300):
         c = time.perf_counter()
         tc.append((b - a) * 1e6)
         tm.append((c - b) * 1e6)
-    return {"plain_1M_count_us_p50": round(float(np.percentile(tc, 50)), 1),
+    from oracle import scan
+    a = time.perf_counter()
+    want = scan.count(t, dg.pred_plain(t, 0))
+    oracle_s = time.perf_counter() - a
+    assert want == n
+    return {"plain_1M_oracle_ns_per_row": round(oracle_s / t.nrows * 1e9, 2),
+            "plain_1M_count_us_p50": round(float(np.percentile(tc, 50)), 1),
             "plain_1M_count_us_p99": round(float(np.percentile(tc, 99)), 1),
             "plain_1M_materialize_us_p50": round(float(np.percentile(tm, 50)), 1),
             "plain_1M_materialize_us_p99": round(float(np.percentile(tm, 99)), 1)}
@@ -412,12 +464,9 @@ def learned_workload(args):
     exact = learned.exact_counts(ctx, dt, [cps[i] for i in idx]) if len(idx) else np.zeros(0, np.uint64)
     host = t.host()
     rng = np.random.default_rng(0)
-    check = [int(i) for i in rng.choice(len(counts), 40, replace=False)] + [int(i) for i in idx[:20]]
-    oracle_errors = 0
-    for j, i in enumerate(check):
-        oracle_errors += int(counts[i]) != scan.count(host, specs[i])
-        if j % 10 == 9:
-            log(f"learned: oracle check {j + 1}/{len(check)}")
+    check = sorted(set(int(i) for i in rng.choice(len(counts), 1000, replace=False)) | set(int(i) for i in idx))
+    got, workers, oracle_s = oracle_counts(host, specs, check, "learned")
+    oracle_errors = sum(int(counts[i]) != got[i] for i in check)
     flops = 4096 * 2 * (64 * 256 + 2 * 256 * 256 + 256)
     print(json.dumps({
         "workload": "learned gate: 100M x 6 table, %d training predicates, held-out batch of 4096" % ntrain,
@@ -428,7 +477,9 @@ def learned_workload(args):
         "qerror_median": float(np.median(q)), "qerror_p90": float(np.quantile(q, 0.9)),
         "qerror_p99": float(np.quantile(q, 0.99)), "qerror_max": float(q.max()), "beta": beta,
         "routed_fraction": float(route.mean()), "routed_count_errors": int((exact != counts[idx]).sum()),
-        "oracle_checked": len(check), "oracle_errors": oracle_errors, "predicate_gen_s": round(gen_s, 1)}),
+        "oracle_checked": len(check), "oracle_checked_note": "1000 random labels + every routed test predicate",
+        "oracle_errors": oracle_errors, "oracle_processes": workers, "oracle_s": round(oracle_s, 1),
+        "predicate_gen_s": round(gen_s, 1)}),
         flush=True)
 
 
@@ -478,6 +529,15 @@ def planning_workload(args):
     est_sel = np.where(r, gated["counts"] / np.array([t.nrows for t in tabs], np.float64), np.exp(gated["est"]))
     agree = np.mean([a == b for a, b in zip(planning.plans(exact_sel, [t.nrows for t in tabs], gcfg),
                                             planning.plans(est_sel, [t.nrows for t in tabs], gcfg))])
+    # the oracle checks the exact counts: every selection on R and S, a
+    # seeded sample of 48 on the 1B-row P
+    oracle_errors, oracle_checked = 0, 0
+    for ti, tab in enumerate(tabs):
+        idx = list(range(nq)) if ti < 2 else sorted(np.random.default_rng(5).choice(nq, 48, replace=False).tolist())
+        log(f"planning: oracle on table {ti} ({len(idx)} selections)")
+        got, workers, _ = oracle_counts(tab.host(), [q[ti] for q in queries], idx, f"planning table {ti}")
+        oracle_errors += sum(int(plain["counts"][i, ti]) != got[i] for i in idx)
+        oracle_checked += len(idx)
     strip = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()
                        if k not in ("counts", "est", "routed")}
     print(json.dumps({
@@ -488,7 +548,9 @@ def planning_workload(args):
         "batched_speedup_vs_plain": round(batched["predicates_per_s"] / plain["predicates_per_s"], 2),
         "routed_count_errors": int((gated["counts"][r] != plain["counts"][r]).sum()),
         "batched_count_errors": int((batched["counts"] != plain["counts"]).sum()),
-        "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1)}), flush=True)
+        "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1),
+        "oracle_checked": oracle_checked, "oracle_errors": oracle_errors,
+        "oracle_note": "every selection on the 10M and 100M tables, 48 seeded ones on the 1B table"}), flush=True)
 
 
 if __name__ == "__main__":
