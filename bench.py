@@ -524,6 +524,15 @@ def planning_workload(args):
     gated = w.run_batched(gate=True, estimators=ests, gcfg=gcfg)
     gated_p = w.run_batched(gate=True, estimators=ests,
                             gcfg=planning.GateConfig(beta=1.5, exact_probe=True))
+    # capacity: the same queries offered 50x faster (100,000/s), so every mode
+    # is saturated and predicates/s measures what it can sustain
+    log("planning: saturated arrivals")
+    ws = planning.Workload(ctx, dts, queries, arrivals / 50.0)
+    sat_plain = ws.run_plain()
+    sat_batched = ws.run_batched()
+    sat_gated = ws.run_batched(gate=True, estimators=ests, gcfg=gcfg)
+    assert np.array_equal(sat_batched["counts"], plain["counts"])
+    assert np.array_equal(sat_gated["counts"][sat_gated["routed"]], plain["counts"][sat_gated["routed"]])
     r = gated["routed"]
     exact_sel = plain["counts"] / np.array([t.nrows for t in tabs], np.float64)
     est_sel = np.where(r, gated["counts"] / np.array([t.nrows for t in tabs], np.float64), np.exp(gated["est"]))
@@ -545,6 +554,11 @@ def planning_workload(args):
         "plain": strip(plain), "batched": strip(batched), "batched_gate": strip(gated),
         "batched_gate_exact_probe": strip(gated_p),
         "gate_speedup_vs_plain": round(gated["predicates_per_s"] / plain["predicates_per_s"], 2),
+        "saturated_100k_per_s": {"plain": strip(sat_plain), "batched": strip(sat_batched), "batched_gate": strip(sat_gated),
+                                 "gate_speedup_vs_plain": round(sat_gated["predicates_per_s"] /
+                                                                sat_plain["predicates_per_s"], 2),
+                                 "batched_speedup_vs_plain": round(sat_batched["predicates_per_s"] /
+                                                                   sat_plain["predicates_per_s"], 2)},
         "batched_speedup_vs_plain": round(batched["predicates_per_s"] / plain["predicates_per_s"], 2),
         "routed_count_errors": int((gated["counts"][r] != plain["counts"][r]).sum()),
         "batched_count_errors": int((batched["counts"] != plain["counts"]).sum()),
