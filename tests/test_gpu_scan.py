@@ -239,3 +239,28 @@ def test_materialize_reuse_and_density_mix(ctx):
     mat("mixed")                          # twice in a row
     for k in reversed(order):             # materialize without a preceding count
         mat(k)
+
+
+def test_max_rows_closed_forms(ctx):
+    """The largest table the ABI allows (2^31 - 1 rows, row ids are int32):
+    A = row index, so count(A < k) = k, a BETWEEN near the end selects known
+    rows, and the batched kernel agrees."""
+    import torch
+    n = 2**31 - 1
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    dt = esc.Table(n, [dg.INT32], [a])
+    for k in (0, 1, 12_345_678, n - 5, n):
+        assert ctx.count(dt, esc.Pred(dt, ("lt", 0, k))) == k
+    assert ctx.count(dt, esc.Pred(dt, ("gt", 0, n - 2))) == 1
+    p = esc.Pred(dt, ("between", 0, n - 1000, n - 1))
+    ids = torch.empty(1000, dtype=torch.int32, device="cuda")
+    out = torch.empty(1000, dtype=torch.int32, device="cuda")
+    assert ctx.count(dt, p) == 1000
+    assert ctx.materialize(dt, p, [0], ids, [out], 1000) == 1000
+    want = torch.arange(n - 1000, n, dtype=torch.int32, device="cuda")
+    assert torch.equal(ids, want) and torch.equal(out, want)
+    preds = [("lt", 0, 7), ("between", 0, 2**30, 2**30 + 99), ("gt", 0, n - 11), ("eq", 0, n - 1)]
+    b = esc.Batch(ctx, [dt], [esc.Pred(dt, q) for q in preds], [0] * len(preds))
+    assert b.count().tolist() == [7, 100, 10, 1]
+    del b, a, ids, out, want
+    torch.cuda.empty_cache()
