@@ -169,8 +169,8 @@ def main():
     if args.planning:
         return planning_workload(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "but not implemented, so --gpus must be 1"}))
+        print(json.dumps({"error": "runs on one GPU only (sharding by rows across GPUs is designed, "
+                                   "not implemented): --gpus must be 1"}))
         sys.exit(2)
 
     import torch
