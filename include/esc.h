@@ -217,6 +217,16 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                     void *const *dev_proj_out, uint64_t capacity,
                     void *dev_ws, size_t ws_bytes, void *stream, uint64_t *out_count);
 
+/* Same materialization, asynchronous: everything is enqueued on `stream` and
+ * nothing waits.  The full count is written to device memory `dev_count`
+ * (8 bytes) in stream order; when it exceeds `capacity` only the first
+ * `capacity` rows were written (the caller compares after synchronizing).
+ * Argument checks and the workspace rules are those of esc_materialize. */
+int esc_materialize_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+                          const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
+                          void *const *dev_proj_out, uint64_t capacity,
+                          void *dev_ws, size_t ws_bytes, void *stream, uint64_t *dev_count);
+
 /* ------------------------------------------------------------------ batched
  *
  * Section 2 runs one selectivity sub-query for every table that carries a

@@ -155,6 +155,8 @@ int esc_ctx_create(int device, esc_ctx **out)
     if (r) c->bpc = atoi(r);
     r = getenv("ESC_MAT_BLOCKS_PER_CU");
     if (r) c->mat_bpc = atoi(r);
+    r = getenv("ESC_DENSE_SHIFT");
+    if (r && atoi(r) >= 0 && atoi(r) <= 12) c->dense_shift = atoi(r);
     *out = c;
     return ESC_OK;
 }
@@ -254,11 +256,16 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *d
     return count_launch(ctx, t, p, dev_ws, ws_bytes, (hipStream_t)stream, (unsigned long long *)dev_count, false);
 }
 
-int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols, int nproj,
-                    int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity, void *dev_ws,
-                    size_t ws_bytes, void *stream, uint64_t *out_count)
+}  // extern "C"
+
+__global__ void copy_u64_kernel(unsigned long long *dst, const unsigned long long *src) { *dst = *src; }
+
+// Enqueues count (unless the workspace holds this predicate's tiles), scan
+// and write on the stream; the total count lands in *dev_total (device).
+static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols,
+                              int nproj, int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity,
+                              void *dev_ws, size_t ws_bytes, hipStream_t s, unsigned long long *dev_total)
 {
-    if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
     if (!ctx || !t || !p) return fail(ESC_ERR_INVALID, "null handle");
     const int rpt = count_rpt(ctx->count_variant, p->prog.nslots);
     const WsLayout L = ws_layout(t->nrows, rpt);
@@ -278,34 +285,51 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
         pa.src[q] = (const uint32_t *)t->cols[c];
         pa.dst[q] = capacity > 0 ? (uint32_t *)dev_proj_out[q] : nullptr;
     }
-    if ((P.flags & P_ALWAYS_FALSE) || t->nrows == 0) {
-        *out_count = 0;
-        return ESC_OK;
-    }
     if ((rc = set_device(ctx->device))) return rc;
-    hipStream_t s = (hipStream_t)stream;
     WsHeader *h = (WsHeader *)dev_ws;
-    uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
-    uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
-    const uint32_t *bits = (const uint32_t *)((char *)dev_ws + L.bits_off);
-    // pass 1: per-wave-tile counts and lane masks, unless the preceding count left them
-    if (!tiles_valid(ctx, dev_ws, t, p, rpt)) {
-        if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true))) return rc;
-    }
-    // pass 2: offsets in row order
-    launch_scan(tiles, L.ntiles, offsets, h, s);
-    // pass 3: write
-    if (capacity > 0) {
-        WriteFn fn = write_fn(rpt);
-        const int occ = occupancy((const void *)fn, kScanBlock, 0);
-        int64_t grid = (int64_t)ctx->num_cus * (ctx->mat_bpc > 0 ? std::min(ctx->mat_bpc, occ) : occ);
-        const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
-        if (grid > blocks_needed) grid = blocks_needed;
-        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, bits, offsets, t->nrows, pa, dev_rowids,
-                           (unsigned long long)capacity);
+    if ((P.flags & P_ALWAYS_FALSE) || t->nrows == 0) {
+        hipLaunchKernelGGL(store_u64_kernel, dim3(1), dim3(1), 0, s, dev_total, 0ull);
+    } else {
+        uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
+        uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
+        const uint32_t *bits = (const uint32_t *)((char *)dev_ws + L.bits_off);
+        // pass 1: per-wave-tile counts and lane masks, unless the preceding count left them
+        if (!tiles_valid(ctx, dev_ws, t, p, rpt)) {
+            if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true))) return rc;
+        }
+        // pass 2: offsets in row order (total in h->result)
+        launch_scan(tiles, L.ntiles, offsets, h, s);
+        // pass 3: write
+        if (capacity > 0) {
+            WriteFn fn = write_fn(rpt);
+            const int occ = occupancy((const void *)fn, kScanBlock, 0);
+            int64_t grid = (int64_t)ctx->num_cus * (ctx->mat_bpc > 0 ? std::min(ctx->mat_bpc, occ) : occ);
+            const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
+            if (grid > blocks_needed) grid = blocks_needed;
+            const uint32_t dense_min = std::max<uint32_t>(1u, (uint32_t)(64 * rpt) >> ctx->dense_shift);
+            hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, bits, offsets, t->nrows, pa,
+                               dev_rowids, (unsigned long long)capacity, dense_min);
+        }
+        if (dev_total != &h->result) hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(1), 0, s, dev_total, &h->result);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "materialize kernel launch");
+    return e == hipSuccess ? ESC_OK : hip_fail(e, "materialize kernel launch");
+}
+
+extern "C" {
+
+int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols, int nproj,
+                    int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity, void *dev_ws,
+                    size_t ws_bytes, void *stream, uint64_t *out_count)
+{
+    if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
+    if (!ctx || !dev_ws || ws_bytes < sizeof(WsHeader)) return fail(ESC_ERR_INVALID, "null handle or workspace");
+    hipStream_t s = (hipStream_t)stream;
+    WsHeader *h = (WsHeader *)dev_ws;
+    int rc = materialize_launch(ctx, t, p, proj_cols, nproj, dev_rowids, dev_proj_out, capacity, dev_ws, ws_bytes, s,
+                                &h->result);
+    if (rc) return rc;
+    hipError_t e;
     if ((e = hipMemcpyAsync(ctx->pinned, &h->result, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -314,6 +338,15 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     if (total > capacity)
         return fail(ESC_ERR_CAPACITY, "%llu rows qualify, capacity %llu", total, (unsigned long long)capacity);
     return ESC_OK;
+}
+
+int esc_materialize_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols, int nproj,
+                          int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity, void *dev_ws,
+                          size_t ws_bytes, void *stream, uint64_t *dev_count)
+{
+    if (!dev_count) return fail(ESC_ERR_INVALID, "null dev_count");
+    return materialize_launch(ctx, t, p, proj_cols, nproj, dev_rowids, dev_proj_out, capacity, dev_ws, ws_bytes,
+                              (hipStream_t)stream, (unsigned long long *)dev_count);
 }
 
 }  // extern "C"

@@ -42,7 +42,8 @@ struct WsHeader {
 static_assert(sizeof(WsHeader) == 64, "workspace header is 64 bytes");
 
 typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsigned long long *, const TileOut);
-typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjArgs, int32_t *, unsigned long long);
+typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjArgs, int32_t *, unsigned long long,
+                        uint32_t);
 
 CountFn count_fn(int nslots, int variant, bool udf);
 int count_rpt(int variant, int nslots);

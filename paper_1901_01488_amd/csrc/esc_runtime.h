@@ -13,6 +13,7 @@ struct esc_ctx {
     int nt = 1;                             // streaming loads in the scans
     int bpc = 1;                            // count-kernel blocks per CU (0: occupancy)
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)
+    int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
 };
 
 namespace esc {

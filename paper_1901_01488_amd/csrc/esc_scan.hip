@@ -180,12 +180,11 @@ __device__ __forceinline__ void stage_and_flush(uint32_t *buf, uint32_t nib, con
 // rows) is compacted in LDS (rank of a row = lanes below, from ballot masks,
 // then e) and each output column is written as one contiguous run.  A
 // projected column is read with the tile's coalesced 16-byte loads when the
-// tile is dense enough that every 64-byte line holds a qualifying row on
-// average, else gathered row by row.
+// tile has at least dense_min qualifying rows, else gathered row by row.
 template <int RPT>
 __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_bits, const uint32_t *offsets,
                                                            int64_t n, const ProjArgs pa, int32_t *rowids,
-                                                           unsigned long long cap)
+                                                           unsigned long long cap, uint32_t dense_min)
 {
     constexpr int TILE = kWave * RPT;
     constexpr int NW = kScanBlock / kWave;
@@ -201,7 +200,7 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_
         if (o0 == o1 || o0 >= cap) continue;   // wave-uniform
         const int64_t base = t * TILE;
         const bool full = base + TILE <= n;
-        const bool dense = full && (o1 - o0) * 16u >= (uint32_t)TILE;
+        const bool dense = full && o1 - o0 >= dense_min;
         const uint32_t bits = tile_bits[t * kWave + lane];
         unsigned long long p = o0;   // output position of the chunk's first qualifying row
 #pragma unroll

@@ -95,6 +95,8 @@ def lib():
             "esc_count_async": ([vp, vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
             "esc_materialize": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, P(u64)],
                                 ctypes.c_int),
+            "esc_materialize_async": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, vp],
+                                      ctypes.c_int),
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
@@ -316,6 +318,16 @@ class Context:
             return out.value
         check(rc)
         return out.value
+
+    def materialize_async(self, table: Table, pred: Pred, proj, rowids, outs, capacity, dev_count, ws, stream=None):
+        """Enqueues the materialization; the full count goes to the device
+        tensor dev_count (one int64) in stream order."""
+        pj = np.asarray(proj, np.int32)
+        optrs = (ctypes.c_void_p * max(len(outs), 1))(*[o.data_ptr() for o in outs])
+        check(lib().esc_materialize_async(self.h, table.h, pred.h, pj.ctypes.data if len(pj) else None, len(pj),
+                                          ctypes.c_void_p(rowids.data_ptr()) if rowids is not None else None,
+                                          optrs, int(capacity), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream_handle(stream), ctypes.c_void_p(dev_count.data_ptr())))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

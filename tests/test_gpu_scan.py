@@ -264,3 +264,38 @@ def test_max_rows_closed_forms(ctx):
     assert b.count().tolist() == [7, 100, 10, 1]
     del b, a, ids, out, want
     torch.cuda.empty_cache()
+
+
+def test_materialize_async_matches_sync(ctx):
+    """esc_materialize_async enqueues the same passes and leaves the count in
+    device memory: rows and projections equal the blocking call's, also with
+    a capacity below the count (first rows written) and for a constant-false
+    predicate."""
+    import torch
+    t = dg.table_star(1_500_001, seed=93)
+    dt = esc.device_table(t)
+    specs = dg.preds_star(t, 6, seed=94) + [("lt", 2, -2**31)]
+    ws_a = ctx.workspace(dt, True, key="async-a")
+    ws_s = ctx.workspace(dt, True, key="async-s")
+    dcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for i, spec in enumerate(specs):
+        p = esc.Pred(dt, spec)
+        n = scan.count(t, spec)
+        for cap in (n, max(n // 3, 1)):
+            ids_a = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+            outs_a = [torch.zeros(max(cap, 1), dtype=dt.cols[j].dtype, device="cuda") for j in dg.STAR_PROJECTION]
+            ids_s = torch.full_like(ids_a, -1)
+            outs_s = [torch.zeros_like(o) for o in outs_a]
+            if i % 2 == 0:
+                assert ctx.count(dt, p, ws=ws_a) == n   # masks reused by the async call
+            ctx.materialize_async(dt, p, dg.STAR_PROJECTION, ids_a, outs_a, cap, dcount, ws_a)
+            torch.cuda.synchronize()
+            assert int(dcount.item()) == n, (i, cap)
+            c = ctx.materialize(dt, p, dg.STAR_PROJECTION, ids_s, outs_s, cap, ws=ws_s, allow_overflow=True)
+            assert c == n
+            k = min(n, cap)
+            assert torch.equal(ids_a[:k], ids_s[:k])
+            for a, b in zip(outs_a, outs_s):
+                assert torch.equal(a[:k].view(torch.int32), b[:k].view(torch.int32))
+            if cap < n:
+                assert bool((ids_a[k:] == -1).all())
