@@ -274,7 +274,8 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        for name, fn in (("plain_latency", lambda: plain_latency(ctx, esc, dg, torch, dev)),
+        for name, fn in (("conjuncts", lambda: conjunct_split(ctx, dt, cps, kern_bytes)),
+                         ("plain_latency", lambda: plain_latency(ctx, esc, dg, torch, dev)),
                          ("batched", lambda: batched_vs_plain(ctx, esc, dg, torch, dev))):
             try:
                 extras.update(fn())
@@ -296,6 +297,27 @@ def main():
         line["cpu_baseline"] = cpu_baseline(t, preds)
     line["extras"] = extras
     print(json.dumps(line), flush=True)
+
+
+def conjunct_split(ctx, dt, cps, kern_bytes, reps=3):
+    """Per-conjunct and prefix counts of the 32 star predicates (one scan
+    each): wall time of the blocking call against the plain count's."""
+    for p in cps:
+        ctx.count_conjuncts(dt, p)
+    tc, tp = [], []
+    for _ in range(reps):
+        a = time.perf_counter()
+        for p in cps:
+            ctx.count_conjuncts(dt, p)
+        tc.append(time.perf_counter() - a)
+        a = time.perf_counter()
+        for p in cps:
+            ctx.count(dt, p)
+        tp.append(time.perf_counter() - a)
+    c, q = float(np.median(tc)), float(np.median(tp))
+    return {"split_conjuncts_GBps": round(sum(kern_bytes) / c / 1e9, 1),
+            "split_conjuncts_ms_per_predicate": round(c / len(cps) * 1e3, 3),
+            "plain_count_ms_per_predicate": round(q / len(cps) * 1e3, 3)}
 
 
 def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):

@@ -57,6 +57,7 @@ typedef enum {
 #define ESC_MAX_IN 64                /* constants in one IN-list */
 #define ESC_MAX_CLAUSES 32           /* conjuncts after conversion to AND-of-ORs */
 #define ESC_MAX_PROJ 8               /* projected columns of one materialization */
+#define ESC_MAX_CONJ 32              /* top-level conjuncts split by esc_count_conjuncts */
 
 /* ------------------------------------------------------------------ predicates
  *
@@ -226,6 +227,18 @@ int esc_materialize_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                           const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
                           void *const *dev_proj_out, uint64_t capacity,
                           void *dev_ws, size_t ws_bytes, void *stream, uint64_t *dev_count);
+
+/* Split selectivities of a conjunction, from one scan: for a predicate
+ * whose root is AND with m children (any other predicate: m = 1),
+ * conj_counts[i] = rows that satisfy child i alone and prefix_counts[i] =
+ * rows that satisfy children 0..i together, so prefix_counts[m-1] is the
+ * predicate's count.  Children are compiled separately (constant folding
+ * applies per child); together they read at most 8 columns.  m <=
+ * ESC_MAX_CONJ and m <= max_out, else ESC_ERR_UNSUPPORTED / ESC_ERR_INVALID;
+ * *out_nconj = m.  Uses device memory of the context; blocks until the
+ * counts are on the host. */
+int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *stream, int max_out,
+                        uint64_t *conj_counts, uint64_t *prefix_counts, int *out_nconj);
 
 /* ------------------------------------------------------------------ batched
  *

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <utility>
+#include <vector>
 
 #include "esc_host.h"
 #include "esc_kernels.h"
@@ -166,6 +167,7 @@ int esc_ctx_destroy(esc_ctx *ctx)
     if (!ctx) return ESC_OK;
     forget_tiles(ctx, nullptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->conj_dev) (void)hipFree(ctx->conj_dev);
     delete ctx;
     return ESC_OK;
 }
@@ -337,6 +339,74 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     *out_count = total;
     if (total > capacity)
         return fail(ESC_ERR_CAPACITY, "%llu rows qualify, capacity %llu", total, (unsigned long long)capacity);
+    return ESC_OK;
+}
+
+int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *stream, int max_out,
+                        uint64_t *conj_counts, uint64_t *prefix_counts, int *out_nconj)
+{
+    if (!ctx || !t || !p || !conj_counts || !prefix_counts || !out_nconj) return fail(ESC_ERR_INVALID, "null argument");
+    if (!t->has_data()) return fail(ESC_ERR_INVALID, "table has no device columns");
+    if (p->schema_dtypes != t->dtypes) return fail(ESC_ERR_INVALID, "predicate was compiled for another schema");
+    std::vector<Program> progs;
+    int nslots = 0, slot_col[kMaxSlots] = {};
+    int rc = split_conjuncts(p, progs, nslots, slot_col);
+    if (rc) return rc;
+    const int m = (int)progs.size();
+    if (m > max_out) return fail(ESC_ERR_INVALID, "%d conjuncts, room for %d", m, max_out);
+    // a conjunct folded to false runs as an empty bitset test on slot 0 (an
+    // always-true one has no instructions and yields every valid row)
+    if (nslots == 0) {
+        nslots = 1;
+        slot_col[0] = 0;
+        for (Program &q : progs) {
+            q.nslots = 1;
+            q.slot_col[0] = 0;
+        }
+    }
+    for (Program &q : progs)
+        if (q.flags & P_ALWAYS_FALSE) {
+            q.flags &= ~P_ALWAYS_FALSE;
+            q.ninsn = 1;
+            q.insn[0] = Insn{T_BITSET, 0, (uint8_t)(F_SINGLE | F_END_CLAUSE), 0, 0, 0, 0};
+        }
+    if ((rc = set_device(ctx->device))) return rc;
+    const size_t counters_off = (size_t)kMaxConj * sizeof(Program);
+    const size_t bytes = counters_off + 2 * kMaxConj * sizeof(unsigned long long);
+    hipError_t e;
+    if (!ctx->conj_dev && (e = hipMalloc(&ctx->conj_dev, bytes)) != hipSuccess) {
+        ctx->conj_dev = nullptr;
+        return fail(ESC_ERR_OOM, "device memory for conjunct counts: %s", hipGetErrorString(e));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Program *d_progs = (Program *)ctx->conj_dev;
+    unsigned long long *d_out = (unsigned long long *)((char *)ctx->conj_dev + counters_off);
+    if ((e = hipMemcpyAsync(d_progs, progs.data(), m * sizeof(Program), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "upload conjunct programs");
+    launch_zero(d_out, 2 * kMaxConj, s);
+    bool udf = false;
+    for (const Program &q : progs) udf |= (q.flags & P_HAS_UDF) != 0;
+    if (t->nrows > 0) {
+        ColPtrs cp{};
+        cp.nt = ctx->nt;
+        for (int c = 0; c < nslots; c++) cp.p[c] = (const uint32_t *)t->cols[slot_col[c]];
+        ConjFn fn = conj_fn(nslots, udf);
+        const int occ = occupancy((const void *)fn, kScanBlock, 0);
+        int64_t grid = (int64_t)ctx->num_cus * occ;
+        const int64_t blocks_needed = (t->nrows + 16 * kScanBlock - 1) / (16 * kScanBlock);
+        if (grid > blocks_needed) grid = blocks_needed;
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, d_progs, m, cp, t->nrows, d_out);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "conjunct kernel launch");
+    if ((e = hipMemcpyAsync(ctx->pinned, d_out, 2 * kMaxConj * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (int i = 0; i < m; i++) {
+        conj_counts[i] = ctx->pinned[i];
+        prefix_counts[i] = ctx->pinned[kMaxConj + i];
+    }
+    *out_nconj = m;
     return ESC_OK;
 }
 

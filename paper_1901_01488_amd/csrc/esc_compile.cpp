@@ -430,6 +430,76 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     return ESC_OK;
 }
 
+// Number of nodes of the pre-order subtree starting at pos (0 on a malformed
+// array; the tree was validated when the predicate was compiled).
+static int subtree_size(const std::vector<esc_node> &nodes, int pos)
+{
+    if (pos >= (int)nodes.size()) return 0;
+    const esc_node &n = nodes[pos];
+    int size = 1;
+    if (n.op == ESC_AND || n.op == ESC_OR)
+        for (int i = 0; i < n.nchild; i++) {
+            const int k = subtree_size(nodes, pos + size);
+            if (k == 0) return 0;
+            size += k;
+        }
+    return size;
+}
+
+int split_conjuncts(const esc_pred *p, std::vector<Program> &out, int &nslots, int *slot_col)
+{
+    out.clear();
+    esc_table schema;
+    schema.dtypes = p->schema_dtypes;
+    std::vector<std::pair<int, int>> parts;   // [start, size) of each top-level conjunct
+    const esc_node &root = p->nodes[0];
+    if (root.op == ESC_AND) {
+        int pos = 1;
+        for (int i = 0; i < root.nchild; i++) {
+            const int k = subtree_size(p->nodes, pos);
+            if (k == 0) return fail(ESC_ERR_INVALID, "malformed node array");
+            parts.push_back({pos, k});
+            pos += k;
+        }
+    } else {
+        parts.push_back({0, (int)p->nodes.size()});
+    }
+    if ((int)parts.size() > ESC_MAX_CONJ)
+        return fail(ESC_ERR_UNSUPPORTED, "%zu conjuncts (max %d)", parts.size(), ESC_MAX_CONJ);
+    // compile each conjunct, then map its slots onto the union of columns
+    int slot_of[64];
+    for (int c = 0; c < 64; c++) slot_of[c] = -1;
+    nslots = 0;
+    for (auto &pt : parts) {
+        esc_pred q;
+        int rc = compile(&schema, p->nodes.data() + pt.first, pt.second, p->consts.data(), (int)p->consts.size(),
+                         p->udf.data(), (int)p->udf.size(), &q);
+        if (rc) return rc;
+        for (int s = 0; s < q.prog.nslots; s++) {
+            const int c = q.prog.slot_col[s];
+            if (slot_of[c] < 0) {
+                if (nslots == kMaxSlots)
+                    return fail(ESC_ERR_UNSUPPORTED, "conjuncts read more than %d columns", kMaxSlots);
+                slot_of[c] = nslots;
+                slot_col[nslots++] = c;
+            }
+        }
+        out.push_back(q.prog);
+    }
+    for (Program &Q : out) {
+        const Program P = Q;
+        for (int i = 0; i < P.ninsn; i++) {
+            Insn &I = Q.insn[i];
+            const bool udf_op = I.op >= U_LOAD;
+            const bool reads_col = udf_op ? !(I.flags & F_CONST) : !(I.flags & F_SRC_UDF);
+            if (reads_col) I.src = (uint8_t)slot_of[P.slot_col[I.src]];
+        }
+        Q.nslots = nslots;
+        for (int s = 0; s < kMaxSlots; s++) Q.slot_col[s] = s < nslots ? slot_col[s] : 0;
+    }
+    return ESC_OK;
+}
+
 }  // namespace esc
 
 // ---------------------------------------------------------------- C ABI

@@ -40,4 +40,9 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes,
             const esc_const *consts, int nconsts, const esc_udf_insn *udf, int nudf,
             esc_pred *p);
 
+// The top-level conjuncts of p (the children of a root AND; p itself
+// otherwise), each compiled on its own, with their column slots mapped onto
+// one common slot order (nslots, slot_col).
+int split_conjuncts(const esc_pred *p, std::vector<Program> &out, int &nslots, int *slot_col);
+
 }  // namespace esc

@@ -9,6 +9,7 @@
 namespace esc {
 
 constexpr int kScanBlock = 256;
+constexpr int kMaxConj = ESC_MAX_CONJ;
 
 // device pointers of the loaded column slots
 struct ColPtrs {
@@ -48,6 +49,8 @@ typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjA
 CountFn count_fn(int nslots, int variant, bool udf);
 int count_rpt(int variant, int nslots);
 WriteFn write_fn(int rpt);
+typedef void (*ConjFn)(const Program *, int, const ColPtrs, int64_t, unsigned long long *);
+ConjFn conj_fn(int nslots, bool udf);
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s);
 void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s);
 

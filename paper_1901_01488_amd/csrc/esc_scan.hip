@@ -85,6 +85,51 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     }
 }
 
+// ------------------------------------------------------------------ conjuncts
+
+// Split selectivities: every conjunct program runs on each loaded wave tile;
+// a running AND of their masks gives the prefix conjunctions.  Per-wave sums
+// go to LDS, then one u64 atomic per counter per block.  out[i] = rows of
+// conjunct i, out[kMaxConj + i] = rows of conjuncts 0..i.
+template <int K, int RPT, bool UDF>
+__global__ __launch_bounds__(kScanBlock) void conj_kernel(const Program *__restrict__ progs, int nconj,
+                                                          const ColPtrs cp, int64_t n, unsigned long long *out)
+{
+    constexpr int TILE = kWave * RPT;
+    constexpr int KK = K > 0 ? K : 1;
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ uint32_t s_acc[NW][2 * kMaxConj];
+    const int wave = wave_id();
+    for (int i = threadIdx.x; i < NW * 2 * kMaxConj; i += kScanBlock) (&s_acc[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t step = (int64_t)gridDim.x * NW;
+    for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += step) {
+        uint32_t v[KK][RPT];
+        load_vals<K, RPT>(cp, t * TILE, n, v);
+        const uint32_t valid = valid_bits<RPT>(t * TILE, n);
+        uint32_t prefix = valid;
+        for (int i = 0; i < nconj; i++) {
+            const uint32_t m = run_program<K, RPT, UDF>(progs[i], v, valid);
+            prefix &= m;
+            const uint32_t c1 = wave_sum((uint32_t)__popc(m));
+            const uint32_t c2 = wave_sum((uint32_t)__popc(prefix));
+            if (lane_id() == 0) {
+                s_acc[wave][i] += c1;
+                s_acc[wave][kMaxConj + i] += c2;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * kMaxConj; i += kScanBlock) {
+        if ((i % kMaxConj) >= nconj) continue;
+        unsigned long long c = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) c += s_acc[w][i];
+        if (c) atomicAdd(&out[i], c);
+    }
+}
+
 // ------------------------------------------------------------------ scan
 
 // Exclusive scan of m per-tile counts into offsets[0..m]; offsets[m] is the
@@ -274,6 +319,19 @@ CountFn count_fn(int k, int variant, bool udf)
     case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
     default: return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
     }
+}
+
+template <bool UDF, int... Ks>
+constexpr ConjFn conj_table_impl(int k, std::integer_sequence<int, Ks...>)
+{
+    ConjFn t[] = {conj_kernel<Ks, 16, UDF>...};
+    return t[k];
+}
+
+ConjFn conj_fn(int nslots, bool udf)
+{
+    using S = std::make_integer_sequence<int, kMaxSlots + 1>;
+    return udf ? conj_table_impl<true>(nslots, S{}) : conj_table_impl<false>(nslots, S{});
 }
 
 WriteFn write_fn(int rpt)

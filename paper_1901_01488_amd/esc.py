@@ -30,6 +30,7 @@ _UOPS = {"add": U_ADD, "sub": U_SUB, "mul": U_MUL, "mod": U_MOD, "band": U_AND, 
 U_COL, U_CONST = 0, 1
 MLP_NPARAMS = 148481
 MAX_PROJ = 8
+MAX_CONJ = 32
 
 
 class EscError(RuntimeError):
@@ -97,6 +98,7 @@ def lib():
                                 ctypes.c_int),
             "esc_materialize_async": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, vp],
                                       ctypes.c_int),
+            "esc_count_conjuncts": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, P(ctypes.c_int)], ctypes.c_int),
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
@@ -318,6 +320,16 @@ class Context:
             return out.value
         check(rc)
         return out.value
+
+    def count_conjuncts(self, table: Table, pred: Pred, stream=None):
+        """(conjunct counts, prefix counts) of the root AND's children, from
+        one scan."""
+        cc = np.zeros(MAX_CONJ, np.uint64)
+        pc = np.zeros(MAX_CONJ, np.uint64)
+        m = ctypes.c_int()
+        check(lib().esc_count_conjuncts(self.h, table.h, pred.h, _stream_handle(stream), MAX_CONJ,
+                                        cc.ctypes.data, pc.ctypes.data, ctypes.byref(m)))
+        return cc[:m.value].tolist(), pc[:m.value].tolist()
 
     def materialize_async(self, table: Table, pred: Pred, proj, rowids, outs, capacity, dev_count, ws, stream=None):
         """Enqueues the materialization; the full count goes to the device
