@@ -52,95 +52,13 @@ __device__ __forceinline__ uint32_t all_rows()
     return RPT == 32 ? 0xffffffffu : ((1u << RPT) - 1u);
 }
 
-// Row-bit accumulation with add-with-carry (gfx950 VOP3 forms, carries in
-// scalar register pairs).  A compare or subtraction writes one carry per row
-// and an add-with-carry consumes it; four rows are interleaved so that every
-// carry is read three instructions after the one that wrote it (the
-// hardware requires two between a vector write of a scalar register and its
-// use as a carry-in).  No vcc, no select, no wait states.
-
-// m = 16 m + 8 [d3 > s] + 4 [d2 > s] + 2 [d1 > s] + [d0 > s] (unsigned), the
-// borrows of s - d: bit set where a row lies outside the range.
-__device__ __forceinline__ uint32_t shift_in_outside4(uint32_t m, uint32_t s, uint32_t d3, uint32_t d2, uint32_t d1,
-                                                      uint32_t d0)
-{
-    uint32_t t0, t1, t2, t3;
-    uint64_t c0, c1, c2, c3, co;
-    asm("v_sub_co_u32_e64 %[t3], %[c3], %[s], %[d3]\n\t"
-        "v_sub_co_u32_e64 %[t2], %[c2], %[s], %[d2]\n\t"
-        "v_sub_co_u32_e64 %[t1], %[c1], %[s], %[d1]\n\t"
-        "v_sub_co_u32_e64 %[t0], %[c0], %[s], %[d0]\n\t"
-        "v_addc_co_u32_e64 %[m], %[co], %[m], %[m], %[c3]\n\t"
-        "v_addc_co_u32_e64 %[m], %[co], %[m], %[m], %[c2]\n\t"
-        "v_addc_co_u32_e64 %[m], %[co], %[m], %[m], %[c1]\n\t"
-        "v_addc_co_u32_e64 %[m], %[co], %[m], %[m], %[c0]"
-        : [m] "+v"(m), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [c0] "=&s"(c0),
-          [c1] "=&s"(c1), [c2] "=&s"(c2), [c3] "=&s"(c3), [co] "=&s"(co)
-        : [s] "s"(s), [d0] "v"(d0), [d1] "v"(d1), [d2] "v"(d2), [d3] "v"(d3));
-    return m;
-}
-
-// a_i += [x_i == k] for four rows (integer or float equality).
-template <bool F32>
-__device__ __forceinline__ void count_eq4(uint32_t &a0, uint32_t &a1, uint32_t &a2, uint32_t &a3, uint32_t k,
-                                          uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3)
-{
-    uint64_t c0, c1, c2, c3, co;
-    if constexpr (F32)
-        asm("v_cmp_eq_f32_e64 %[c0], %[k], %[x0]\n\t"
-            "v_cmp_eq_f32_e64 %[c1], %[k], %[x1]\n\t"
-            "v_cmp_eq_f32_e64 %[c2], %[k], %[x2]\n\t"
-            "v_cmp_eq_f32_e64 %[c3], %[k], %[x3]\n\t"
-            "v_addc_co_u32_e64 %[a0], %[co], 0, %[a0], %[c0]\n\t"
-            "v_addc_co_u32_e64 %[a1], %[co], 0, %[a1], %[c1]\n\t"
-            "v_addc_co_u32_e64 %[a2], %[co], 0, %[a2], %[c2]\n\t"
-            "v_addc_co_u32_e64 %[a3], %[co], 0, %[a3], %[c3]"
-            : [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3), [c0] "=&s"(c0), [c1] "=&s"(c1),
-              [c2] "=&s"(c2), [c3] "=&s"(c3), [co] "=&s"(co)
-            : [k] "s"(k), [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3));
-    else
-        asm("v_cmp_eq_u32_e64 %[c0], %[k], %[x0]\n\t"
-            "v_cmp_eq_u32_e64 %[c1], %[k], %[x1]\n\t"
-            "v_cmp_eq_u32_e64 %[c2], %[k], %[x2]\n\t"
-            "v_cmp_eq_u32_e64 %[c3], %[k], %[x3]\n\t"
-            "v_addc_co_u32_e64 %[a0], %[co], 0, %[a0], %[c0]\n\t"
-            "v_addc_co_u32_e64 %[a1], %[co], 0, %[a1], %[c1]\n\t"
-            "v_addc_co_u32_e64 %[a2], %[co], 0, %[a2], %[c2]\n\t"
-            "v_addc_co_u32_e64 %[a3], %[co], 0, %[a3], %[c3]"
-            : [a0] "+v"(a0), [a1] "+v"(a1), [a2] "+v"(a2), [a3] "+v"(a3), [c0] "=&s"(c0), [c1] "=&s"(c1),
-              [c2] "=&s"(c2), [c3] "=&s"(c3), [co] "=&s"(co)
-            : [k] "s"(k), [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3));
-}
-
-// Set membership: per row the number of equal constants (duplicates in the
-// list only raise it), then one bit per row.
-template <int RPT, bool F32>
-__device__ __forceinline__ uint32_t in_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT])
-{
-    uint32_t a[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; r++) a[r] = 0;
-    for (int k = 0; k < I.b; k++) {
-        const uint32_t kv = kpool[I.a + k];
-#pragma unroll
-        for (int g = 0; g < RPT; g += 4)
-            count_eq4<F32>(a[g], a[g + 1], a[g + 2], a[g + 3], kv, x[g], x[g + 1], x[g + 2], x[g + 3]);
-    }
-    return bits_of<RPT>([&](int r) { return a[r] != 0u; });
-}
-
 template <int RPT>
 __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT])
 {
     switch (I.op) {
     case T_RANGE_I32: {
         const uint32_t lo = (uint32_t)I.a, span = (uint32_t)I.b;
-        static_assert(RPT % 4 == 0, "rows per lane come in fours");
-        uint32_t outside = 0;
-#pragma unroll
-        for (int g = RPT - 4; g >= 0; g -= 4)
-            outside = shift_in_outside4(outside, span, x[g + 3] - lo, x[g + 2] - lo, x[g + 1] - lo, x[g] - lo);
-        return ~outside & all_rows<RPT>();
+        return bits_of<RPT>([&](int r) { return x[r] - lo <= span; });
     }
     case T_RANGE_F32: {
         const float lo = as_f((uint32_t)I.a), hi = as_f((uint32_t)I.b);
@@ -154,10 +72,22 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
             return d < 64u && ((bits >> (d & 63u)) & 1ull);
         });
     }
-    case T_IN_I32:
-        return in_test<RPT, false>(I, kpool, x);
-    case T_IN_F32:
-        return in_test<RPT, true>(I, kpool, x);
+    case T_IN_I32: {
+        uint32_t m = 0;
+        for (int k = 0; k < I.b; k++) {
+            const uint32_t kv = kpool[I.a + k];
+            m |= bits_of<RPT>([&](int r) { return x[r] == kv; });
+        }
+        return m;
+    }
+    case T_IN_F32: {
+        uint32_t m = 0;
+        for (int k = 0; k < I.b; k++) {
+            const float kf = as_f(kpool[I.a + k]);
+            m |= bits_of<RPT>([&](int r) { return as_f(x[r]) == kf; });
+        }
+        return m;
+    }
     }
     return 0u;
 }
