@@ -299,3 +299,42 @@ def test_materialize_async_matches_sync(ctx):
                 assert torch.equal(a[:k].view(torch.int32), b[:k].view(torch.int32))
             if cap < n:
                 assert bool((ids_a[k:] == -1).all())
+
+
+def test_graph_capture_replay(ctx):
+    """esc_count_async and esc_materialize_async enqueue kernels only (no
+    memset or host copy), so they can be captured into a HIP graph; every
+    replay, with eager work and synchronisations between replays, gives the
+    exact count and rows."""
+    import torch
+    t = dg.table_star(1_000_003, seed=98)
+    dt = esc.device_table(t)
+    spec = dg.preds_star(t, 4, seed=99)[2]
+    p = esc.Pred(dt, spec)
+    want_n, want_ids, want_outs = scan.materialize(t, spec, [6])
+    ws_c = ctx.workspace(dt, False, key="graph-count")
+    ws_m = ctx.workspace(dt, True, key="graph-mat")
+    dcount = torch.zeros(1, dtype=torch.int64, device="cuda")
+    dmat = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(max(want_n, 1), dtype=torch.int32, device="cuda")
+    out = torch.empty(max(want_n, 1), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):   # warm-up on the capture stream
+        ctx.count_async(dt, p, dcount, ws_c, stream=s)
+        ctx.materialize_async(dt, p, [6], ids, [out], want_n, dmat, ws_m, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.count_async(dt, p, dcount, ws_c, stream=s)
+        ctx.materialize_async(dt, p, [6], ids, [out], want_n, dmat, ws_m, stream=s)
+    for r in range(5):
+        dcount.zero_()
+        dmat.zero_()
+        ids.fill_(-1)
+        torch.zeros(1 << 20, device="cuda").add_(1)   # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(dcount.item()) == want_n and int(dmat.item()) == want_n, r
+        assert np.array_equal(ids[:want_n].cpu().numpy(), want_ids), r
+        assert np.array_equal(out[:want_n].cpu().numpy().view(np.uint32), want_outs[0].view(np.uint32)), r
