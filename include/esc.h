@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 2
+#define ESC_ABI_VERSION 3
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -169,6 +169,9 @@ typedef struct {
     int32_t ncols;        /* distinct columns read by a scan */
     int32_t constant;     /* 0: data-dependent; 1: always true; -1: always false */
     uint64_t col_mask;    /* bit c set when column c is read (c < 64) */
+    int32_t nhashed;      /* IN-lists tested by a 64-slot table lookup instead of
+                             one compare per constant */
+    int32_t pad;
 } esc_pred_info;
 int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);
 

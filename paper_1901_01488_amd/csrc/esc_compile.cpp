@@ -7,13 +7,17 @@
 //   1. parse and validate the tree, type-check constants against columns;
 //   2. normalise every leaf into one device test (int range, float range,
 //      64-value bitmap, or a set), folding leaves whose value does not
-//      depend on the row (always true / always false);
+//      depend on the row (always true / always false); sets of three or
+//      more keys become slot tables when a 6-bit field of the value
+//      separates the keys (one cross-lane read per row instead of one
+//      compare per key);
 //   3. convert to an AND of OR-clauses by distributing OR over AND -- exact
 //      because the language has no negation;
 //   4. give each referenced column a register slot and emit instructions.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -128,6 +132,54 @@ int int_set(std::vector<int32_t> v, Leaf &L)
     L.test.op = T_IN_I32;
     for (int32_t x : v) L.kvals.push_back((uint32_t)x);
     return ESC_OK;
+}
+
+// ---- slot tables for IN-lists (op T_IN_HASH)
+
+// Slot of key k under rotation r: bits [r+2, r+8) of k, taken cyclically.
+int slot_of_key(uint32_t k, int r)
+{
+    const uint32_t rot = r ? (k >> r) | (k << (32 - r)) : k;
+    return (int)((rot >> 2) & 63u);
+}
+
+// The bit patterns a slot table must hold: the constants, plus -0.0 beside
+// +0.0 for a float list (float equality treats the zeros as one value;
+// NaN constants were already dropped).
+std::vector<uint32_t> slot_keys(const Leaf &L)
+{
+    std::vector<uint32_t> keys = L.kvals;
+    if (L.test.op == T_IN_F32)
+        for (uint32_t k : L.kvals)
+            if (k == 0u) keys.push_back(0x80000000u);
+    return keys;
+}
+
+// First rotation whose slots separate the keys, or -1.
+int slot_rotation(const std::vector<uint32_t> &keys)
+{
+    if (keys.empty() || keys.size() > (size_t)kSlotTable) return -1;
+    for (int r = 0; r < 32; r++) {
+        uint64_t used = 0;
+        bool ok = true;
+        for (uint32_t k : keys) {
+            const uint64_t bit = 1ull << slot_of_key(k, r);
+            ok = ok && !(used & bit);
+            used |= bit;
+        }
+        if (ok) return r;
+    }
+    return -1;
+}
+
+// Smallest IN-list compiled to a slot table (ESC_IN_HASH_MIN; 0 = never).
+// A list of n keys costs n compare-and-pack steps per row; a table lookup
+// costs about two such steps plus one cross-lane read.
+int in_hash_min()
+{
+    const char *e = getenv("ESC_IN_HASH_MIN");
+    if (!e || !*e) return 3;
+    return atoi(e);
 }
 
 // an int32 comparison (EQ/LT/GT/BETWEEN/IN) with constants ks
@@ -357,6 +409,7 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     cnf.erase(std::unique(cnf.begin(), cnf.end()), cnf.end());
     Program &P = p->prog;
     memset(&P, 0, sizeof P);
+    p->nhashed = 0;
     bool is_false = false;
     for (auto &c : cnf) is_false = is_false || c.empty();
     if (is_false) { P.flags = P_ALWAYS_FALSE; return ESC_OK; }
@@ -389,8 +442,55 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
             }
         }
 
+    // IN-lists: each distinct leaf stores its constants once.  Lists of at
+    // least in_hash_min() keys become 64-entry slot tables when a slot field
+    // separates their keys, largest lists first, as long as all IN-lists
+    // still fit the constant pool.
+    std::vector<int> in_leaves;
+    {
+        std::vector<char> seen(C.leaves.size(), 0);
+        for (auto &c : cnf)
+            for (int li : c) {
+                const Insn &t = C.leaves[li].test;
+                if ((t.op == T_IN_I32 || t.op == T_IN_F32) && !seen[li]) {
+                    seen[li] = 1;
+                    in_leaves.push_back(li);
+                }
+            }
+    }
+    int need = 0;
+    for (int li : in_leaves) need += (int)C.leaves[li].kvals.size();
+    if (need > kMaxKpool) return fail(ESC_ERR_UNSUPPORTED, "predicate has more than %d IN constants", kMaxKpool);
+    std::vector<int> rot_of(C.leaves.size(), -1), table_of(C.leaves.size(), -1);
+    int ntables = 0;
+    {
+        const int hmin = in_hash_min();
+        std::vector<int> order = in_leaves;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return C.leaves[x].kvals.size() > C.leaves[y].kvals.size(); });
+        for (int li : order) {
+            const Leaf &L = C.leaves[li];
+            const int n = (int)L.kvals.size();
+            if (hmin <= 0 || n < hmin || need + (kSlotTable - n) > kMaxKpool) continue;
+            const std::vector<uint32_t> keys = slot_keys(L);
+            const int rot = slot_rotation(keys);
+            if (rot < 0) continue;
+            rot_of[li] = rot;
+            table_of[li] = ntables;
+            // every entry holds some key, so an entry equal to x means x is a key
+            uint32_t *tab = P.kpool + kSlotTable * ntables;
+            for (int e = 0; e < kSlotTable; e++) tab[e] = keys[0];
+            for (uint32_t k : keys) tab[slot_of_key(k, rot)] = k;
+            ntables++;
+            need += kSlotTable - n;
+        }
+    }
+    P.ntables = ntables;
+    p->nhashed = ntables;
+
     // emit
-    int ni = 0, nk = 0;
+    int ni = 0, nk = kSlotTable * ntables;
+    std::vector<int> kpool_at(C.leaves.size(), -1);
     auto emit = [&](Insn in) -> int {
         if (ni == kMaxInsns) return fail(ESC_ERR_UNSUPPORTED, "predicate needs more than %d instructions", kMaxInsns);
         P.insn[ni++] = in;
@@ -398,7 +498,8 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     };
     for (auto &c : cnf) {
         for (size_t j = 0; j < c.size(); j++) {
-            const Leaf &L = C.leaves[c[j]];
+            const int li = c[j];
+            const Leaf &L = C.leaves[li];
             if (L.udf) P.flags |= P_HAS_UDF;
             if (L.udf)
                 for (Insn u : L.uops) {
@@ -407,12 +508,18 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
                 }
             Insn t = L.test;
             if (!L.udf) t.src = (uint8_t)slot_of[t.src];
-            if (t.op == T_IN_I32 || t.op == T_IN_F32) {
-                if (nk + (int)L.kvals.size() > kMaxKpool)
-                    return fail(ESC_ERR_UNSUPPORTED, "predicate has more than %d IN constants", kMaxKpool);
-                t.a = nk;
+            if (table_of[li] >= 0) {
+                t.op = T_IN_HASH;
+                t.a = kSlotTable * table_of[li];
+                t.b = rot_of[li];
+                t.c = table_of[li];
+            } else if (t.op == T_IN_I32 || t.op == T_IN_F32) {
+                if (kpool_at[li] < 0) {
+                    kpool_at[li] = nk;
+                    for (uint32_t k : L.kvals) P.kpool[nk++] = k;
+                }
+                t.a = kpool_at[li];
                 t.b = (int32_t)L.kvals.size();
-                for (uint32_t k : L.kvals) P.kpool[nk++] = k;
             }
             if (j + 1 == c.size()) t.flags |= F_END_CLAUSE;
             if (c.size() == 1) t.flags |= F_SINGLE;
@@ -572,6 +679,8 @@ int esc_pred_get_info(const esc_pred *p, esc_pred_info *out)
     out->ncols = p->prog.nslots;
     out->constant = (p->prog.flags & esc::P_ALWAYS_TRUE) ? 1 : (p->prog.flags & esc::P_ALWAYS_FALSE) ? -1 : 0;
     out->col_mask = p->col_mask;
+    out->nhashed = p->nhashed;
+    out->pad = 0;
     return ESC_OK;
 }
 

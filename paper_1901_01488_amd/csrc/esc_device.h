@@ -52,8 +52,36 @@ __device__ __forceinline__ uint32_t all_rows()
     return RPT == 32 ? 0xffffffffu : ((1u << RPT) - 1u);
 }
 
-template <int RPT>
-__device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpool, const uint32_t (&x)[RPT])
+// Slot tables of a program held in registers, one entry per lane: NT =
+// kMaxTables for kernels that run one program throughout (loaded once,
+// before the first tile), NT = 0 for kernels that switch programs (each
+// slot-table test then reads its table from the constant pool).  Named
+// fields rather than an array: a runtime-indexed array would be moved to
+// LDS by the compiler.
+template <int NT>
+struct SlotTabs {
+    uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+    static_assert(NT == 0 || NT == 4, "four slot tables per program");
+};
+
+template <int NT>
+__device__ __forceinline__ SlotTabs<NT> load_tables(const Program &P)
+{
+    SlotTabs<NT> t;
+    if constexpr (NT > 0) {
+        const uint32_t *k = P.kpool + (threadIdx.x & 63u);
+        const int nt = P.ntables;
+        if (nt > 0) t.e0 = k[0];
+        if (nt > 1) t.e1 = k[kSlotTable];
+        if (nt > 2) t.e2 = k[2 * kSlotTable];
+        if (nt > 3) t.e3 = k[3 * kSlotTable];
+    }
+    return t;
+}
+
+template <int RPT, int NT>
+__device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpool, const SlotTabs<NT> &tabs,
+                                             const uint32_t (&x)[RPT])
 {
     switch (I.op) {
     case T_RANGE_I32: {
@@ -87,6 +115,22 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
             m |= bits_of<RPT>([&](int r) { return as_f(x[r]) == kf; });
         }
         return m;
+    }
+    case T_IN_HASH: {
+        // Lane l holds table entry l; each row reads the entry of its slot
+        // from that lane (the permute takes byte addresses, so the slot
+        // field is cut out at bits 2..7).  Needs all 64 lanes active.
+        uint32_t entry;
+        if constexpr (NT > 0) {
+            entry = I.c == 0 ? tabs.e0 : I.c == 1 ? tabs.e1 : I.c == 2 ? tabs.e2 : tabs.e3;
+        } else {
+            entry = kpool[I.a + (threadIdx.x & 63u)];
+        }
+        const uint32_t rot = (uint32_t)I.b;
+        return bits_of<RPT>([&](int r) {
+            const uint32_t addr = __builtin_rotateright32(x[r], rot) & 0xfcu;
+            return (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)entry) == x[r];
+        });
     }
     }
     return 0u;
@@ -154,8 +198,9 @@ __device__ __forceinline__ void run_udf(const Insn &I, const uint32_t (&v)[KK][R
 // Runs the program on the loaded slots: returns valid & P(row) per row slot.
 // UDF = false is the variant for programs without udf instructions (it does
 // not reserve registers for the udf accumulator).
-template <int K, int RPT, bool UDF = true, int KK = (K > 0 ? K : 1)>
-__device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid)
+template <int K, int RPT, bool UDF = true, int NT = 0, int KK = (K > 0 ? K : 1)>
+__device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid,
+                                                const SlotTabs<NT> &tabs = SlotTabs<NT>{})
 {
     uint32_t acc = valid, cm = 0;
     uint32_t u[UDF ? RPT : 1];
@@ -170,10 +215,10 @@ __device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t
                 run_udf<K, RPT>(I, v, u);
                 continue;
             }
-            if (I.flags & F_SRC_UDF) m = run_test<RPT>(I, P.kpool, u);
-            else for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+            if (I.flags & F_SRC_UDF) m = run_test<RPT, NT>(I, P.kpool, tabs, u);
+            else for_slot<K>(I.src, [&](auto C) { m = run_test<RPT, NT>(I, P.kpool, tabs, v[C]); });
         } else {
-            for_slot<K>(I.src, [&](auto C) { m = run_test<RPT>(I, P.kpool, v[C]); });
+            for_slot<K>(I.src, [&](auto C) { m = run_test<RPT, NT>(I, P.kpool, tabs, v[C]); });
         }
         if (I.flags & F_SINGLE) {
             acc &= m;

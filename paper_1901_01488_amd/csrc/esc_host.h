@@ -26,6 +26,7 @@ struct esc_pred {
     std::vector<esc_const> consts;
     std::vector<esc_udf_insn> udf;
     uint64_t col_mask = 0;
+    int nhashed = 0;   // IN-lists compiled to slot tables
 };
 
 namespace esc {

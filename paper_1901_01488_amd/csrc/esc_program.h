@@ -17,6 +17,8 @@ namespace esc {
 constexpr int kMaxSlots = 8;     // distinct columns per predicate
 constexpr int kMaxInsns = 64;
 constexpr int kMaxKpool = 256;   // IN constants per predicate
+constexpr int kSlotTable = 64;   // entries of a slot table (one per lane)
+constexpr int kMaxTables = kMaxKpool / kSlotTable;
 
 enum Op : uint8_t {
     // tests (read slot `src`, or the udf accumulator when F_SRC_UDF)
@@ -25,6 +27,10 @@ enum Op : uint8_t {
     T_IN_I32 = 2,      // x == kpool[a + i] for some i < b
     T_IN_F32 = 3,      // float ==, same layout
     T_BITSET = 4,      // d = (uint32)(x - a); d < 64 && bit d of (uint64)c<<32 | (uint32)b
+    T_IN_HASH = 5,     // kpool[a + h(x)] == x bitwise, h(x) = (rotr(x, b) >> 2) & 63: a
+                       // 64-entry slot table whose keys occupy distinct slots (float
+                       // lists hold both zeros and no NaN, so bit equality is float
+                       // equality); table c of the program, a = 64 * c
     // udf accumulator updates: operand = slot `src`, or constant a (F_CONST)
     U_LOAD = 16, U_ADD, U_SUB, U_MUL, U_MOD, U_AND, U_OR, U_XOR, U_SHL, U_SHR,
 };
@@ -50,7 +56,8 @@ struct Program {
     int32_t nk;
     int32_t flags;
     int32_t nclauses;
-    int32_t pad[3];
+    int32_t ntables;   // slot tables, at kpool[0 .. 64 * ntables)
+    int32_t pad[2];
     int32_t slot_col[kMaxSlots];   // table column of each slot
     Insn insn[kMaxInsns];
     uint32_t kpool[kMaxKpool];

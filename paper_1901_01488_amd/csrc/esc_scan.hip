@@ -50,11 +50,12 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
     const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
+    const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
     uint32_t cnt = 0;   // per lane
     for (int64_t t = first; t < ntiles; t += step) {
         uint32_t v[KK][RPT];
         load_vals<K, RPT>(cp, t * TILE, n, v);
-        const uint32_t bits = run_program<K, RPT, UDF>(P, v, valid_bits<RPT>(t * TILE, n));
+        const uint32_t bits = run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(t * TILE, n), tabs);
         const uint32_t c = (uint32_t)__popc(bits);
         if (to.counts) {
             const uint32_t w = wave_sum(c);

@@ -59,13 +59,16 @@ class UdfInsn(ctypes.Structure):
 
 class PredInfo(ctypes.Structure):
     _fields_ = [("nclauses", ctypes.c_int32), ("ninsns", ctypes.c_int32), ("ncols", ctypes.c_int32),
-                ("constant", ctypes.c_int32), ("col_mask", ctypes.c_uint64)]
+                ("constant", ctypes.c_int32), ("col_mask", ctypes.c_uint64), ("nhashed", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
+
+ABI_VERSION = 3   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -121,6 +124,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = res
+        if L.esc_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.esc_abi_version()}, this binding needs "
+                              f"{ABI_VERSION}: rebuild it with `python -m paper_1901_01488_amd.build`")
         _lib = L
     return _lib
 
@@ -240,7 +246,7 @@ class Pred:
         i = PredInfo()
         check(lib().esc_pred_get_info(self.h, ctypes.byref(i)))
         return {"nclauses": i.nclauses, "ninsns": i.ninsns, "ncols": i.ncols, "constant": i.constant,
-                "col_mask": i.col_mask}
+                "col_mask": i.col_mask, "nhashed": i.nhashed}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

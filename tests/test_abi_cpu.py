@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 30
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    assert L.esc_abi_version() == 2
+    assert L.esc_abi_version() == 3
 
 
 @pytest.fixture(scope="module")
@@ -189,3 +189,28 @@ def test_ctx_without_gpu():
         pass
     h = ctypes.c_void_p()
     assert esc.lib().esc_ctx_create(0, ctypes.byref(h)) == esc.ERR_HIP
+
+
+def test_in_slot_tables(schema, monkeypatch):
+    """IN-lists of three or more sparse keys become slot-table lookups when a
+    6-bit field separates the keys; otherwise, or when the constant pool
+    cannot hold another 64-entry table, they stay compare lists."""
+    info = lambda s: esc.Pred(schema, s).info()
+    assert info(("in", 0, [5, 1000, 77777]))["nhashed"] == 1
+    assert info(("in", 0, [5, 1000]))["nhashed"] == 0              # two compares are cheaper
+    assert info(("in", 0, list(range(0, 640, 10))))["nhashed"] == 1  # 64 keys, one per slot
+    # 0, 1 and 65536: every cyclic 6-bit field misses bit 0 or bit 16, so one
+    # pair of keys always shares a slot
+    assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 0
+    # float lists: a zero constant needs both zero patterns (two slots)
+    assert info(("in", 2, [np.float32(v) for v in (0.0, 2.5, -7.0)]))["nhashed"] == 1
+    # pool budget (256 constants): 64 + 4 * 3 as lists leave 180, and each
+    # table takes 61 more, so two of the four short lists become tables
+    lists = [("in", c, [10 + i, 5000 + i, 900000 + i]) for i, c in enumerate((0, 1, 3, 0))]
+    big = ("in", 1, [7 * i * i + 3 for i in range(64)])
+    pred = ("and", lists + [big])
+    i = info(pred)
+    assert i["nhashed"] == (1 if info(big)["nhashed"] else 0) + 2
+    monkeypatch.setenv("ESC_IN_HASH_MIN", "0")
+    assert info(pred)["nhashed"] == 0
+    assert info(("in", 0, [5, 1000, 77777]))["nhashed"] == 0

@@ -338,3 +338,51 @@ def test_graph_capture_replay(ctx):
         assert int(dcount.item()) == want_n and int(dmat.item()) == want_n, r
         assert np.array_equal(ids[:want_n].cpu().numpy(), want_ids), r
         assert np.array_equal(out[:want_n].cpu().numpy().view(np.uint32), want_outs[0].view(np.uint32)), r
+
+
+def test_in_slot_tables(ctx, monkeypatch):
+    """IN-lists compiled to slot tables count exactly what the oracle counts,
+    and what the compare-list form counts, on data built to hit the table
+    slots of the keys with other values (keys with one bit flipped), on
+    float lists holding zeros, NaN and infinities, and on 3..64-key lists."""
+    rng = np.random.default_rng(4242)
+    n = 200_003
+    keys = rng.integers(-2**31, 2**31, 64, dtype=np.int64).astype(np.int32)
+    step4 = (np.arange(64, dtype=np.int64) * 4 + 1_000_000).astype(np.int32)   # one key per slot
+    flips = (keys.view(np.uint32) ^ (np.uint32(1) << rng.integers(0, 32, 64).astype(np.uint32))).view(np.int32)
+    icol = np.concatenate([keys, flips, step4, step4 + 2, rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)])
+    fvals = np.array([0.0, -0.0, np.nan, -np.nan, np.inf, -np.inf, 1.0, -1.0, 2.5, 1e-45, -1e-45, 3.4e38], np.float32)
+    fbits = np.concatenate([fvals.view(np.uint32), np.array([0x7fc00001, 0xffc12345], np.uint32)])
+    fcol = np.concatenate([fbits.view(np.float32), rng.standard_normal(64).astype(np.float32)])
+    m = len(icol)
+    icol = rng.permutation(np.resize(icol, m))
+    fcol = rng.choice(fcol, m)
+    t = dg.Table("slots", m, [dg.INT32, dg.FLOAT32], [icol, fcol], ["u", "u"], [None, None])
+    dt = esc.device_table(t)
+    preds = []
+    for w in (3, 4, 5, 7, 10, 12, 20, 33, 64):
+        preds.append(("in", 0, [int(v) for v in rng.choice(keys, w, replace=False)]))
+    preds += [("in", 0, [int(v) for v in step4]), ("in", 0, [int(v) for v in step4[::3]]),
+              ("in", 0, [0, 1, 65536]),   # no separating field: stays a compare list
+              ("in", 1, [np.float32(0.0), np.float32(2.5), np.float32(np.inf)]),
+              ("in", 1, [np.float32(-0.0), np.float32(1e-45), np.float32(-1.0), np.float32(np.nan)]),
+              ("in", 1, [np.float32(v) for v in fvals]),
+              ("in", 1, [np.float32(v) for v in rng.choice(fcol, 9)]),
+              ("or", [("in", 0, [int(v) for v in keys[:6]]), ("in", 1, [np.float32(1.0), np.float32(-1.0), np.float32(0.0)])]),
+              ("udf", ("add", ("col", 0), ("const", 7)), ("in", [int(v) + 7 for v in keys[10:16]]))]
+    hashed = 0
+    for p in preds:
+        want = scan.count(t, p)
+        cp = esc.Pred(dt, p)
+        hashed += cp.info()["nhashed"]
+        assert ctx.count(dt, cp) == want, p
+        n_gpu, c, ids, outs = gpu_materialize(ctx, dt, p, [0, 1])
+        wc, wids, wouts = scan.materialize(t, p, [0, 1])
+        assert n_gpu == c == wc == want, p
+        assert_same_rows(ids, outs, wids, wouts)
+    assert hashed >= len(preds) - 2
+    monkeypatch.setenv("ESC_IN_HASH_MIN", "0")
+    for p in preds:
+        cp = esc.Pred(dt, p)
+        assert cp.info()["nhashed"] == 0
+        assert ctx.count(dt, cp) == scan.count(t, p), p
