@@ -452,8 +452,7 @@ def learned_workload(args):
     log("learned: table")
     t = dg.table_learned(n, device=dev)
     dt = esc.Table(t.nrows, t.dtypes, t.cols)
-    cmin = [c.min().item() for c in t.cols]
-    cmax = [c.max().item() for c in t.cols]
+    catalog = learned.Catalog.of(t, seed=dg.pred_seed(3) + 1)
     ntrain, nval, ntest = args.train_preds, 8192, 4096
     log("learned: predicates")
     t0 = time.perf_counter()
@@ -466,10 +465,10 @@ def learned_workload(args):
     counts = learned.exact_counts(ctx, dt, cps)
     label_s = time.perf_counter() - t0
     log("learned: features + training")
-    x = esc.featurize(dt, cps, cmin, cmax)
+    est = learned.Estimator(ctx, dt, catalog, dg.mlp_init(dg.MLP_SEED))
+    x = est.features(cps)
     y = learned.labels(counts, n)
     tr, va, te = slice(0, ntrain), slice(ntrain, ntrain + nval), slice(ntrain + nval, None)
-    est = learned.Estimator(ctx, dt, cmin, cmax, dg.mlp_init(dg.MLP_SEED))
     phases = [(20, 1e-3), (10, 2e-4), (10, 4e-5)]
     loss, train_s = est.fit(x[tr], y[tr], phases, batch=256, order_seed=dg.MLP_SEED)
     beta = learned.validation_beta(est.predict(x[va]), counts[va], n)
@@ -535,9 +534,7 @@ def planning_workload(args):
         specs = dg.preds_mixed(t, train_n[i], seed=dg.pred_seed(4) + 100 + i, min_conj=2, max_conj=6)
         cps = [esc.Pred(dt, p) for p in specs]
         cnt = learned.exact_counts(ctx, dt, cps)
-        cmin = [c.min().item() for c in t.cols]
-        cmax = [c.max().item() for c in t.cols]
-        e = learned.Estimator(ctx, dt, cmin, cmax, dg.mlp_init(dg.MLP_SEED))
+        e = learned.Estimator(ctx, dt, learned.Catalog.of(t, seed=11 + i), dg.mlp_init(dg.MLP_SEED))
         x = e.features(cps)
         e.train(x, learned.labels(cnt, t.nrows), epochs=20, batch=1024, lr=1e-3, order_seed=11 + i)
         ests.append(e)

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 3
+#define ESC_ABI_VERSION 4
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -278,13 +278,23 @@ int esc_batch_destroy(esc_batch *b);
 
 /* ------------------------------------------------------------------ learned gate
  *
- * Featurization of predicates into 64 float32 values:
- * per column c < 6: [present, lo, hi, is_eq, is_lt, is_gt, is_between, is_in,
- * in_size/16, in_or] then [n_conj/6, n_or/6, has_udf, n_leaves/16]; bounds
- * normalised with the catalog minimum / maximum of each column (col_min /
- * col_max, in the column's dtype).  Host only. */
+ * Featurization of predicates into 64 float32 values: for each column c < 6
+ *   [lsel, lo, hi, is_eq, is_lt, is_gt, is_between, in_mass, in_size/16, in_or]
+ * then [n_conj/6, n_or/6, has_udf, n_leaves/16].  Bounds are fractions of
+ * rows under a smoothed empirical CDF of the column, built from its catalog
+ * minimum and maximum (col_min / col_max) and a row sample: col_sample holds
+ * sample_size values per column for columns 0 .. min(ncols, 6) - 1, in the
+ * column's dtype, any order (sample_size 0: no sample, the CDF is linear
+ * between minimum and maximum).  lo / hi: the range the conjunction leaves
+ * to the column (a cross-column OR bounds each of its columns that no plain
+ * conjunct bounds); lsel = -ln(max(est, 1e-9)) / -ln(1e-9), est = hi - lo
+ * (or the IN mass when smaller); in_mass: the CDF mass of the IN constants;
+ * in_or: ordinal / 4 of the conjunct holding the OR (0 outside ORs).  Host
+ * only.  Errors: ESC_ERR_INVALID (null arguments, negative sample_size,
+ * minimum above maximum, a predicate compiled for another schema). */
 int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
-                  const esc_pred *const *preds, int npreds, float *host_out);
+                  const esc_value *col_sample, int sample_size, const esc_pred *const *preds, int npreds,
+                  float *host_out);
 
 /* MLP 64 -> 256 -> 256 -> 256 -> 1 (ReLU) predicting ln(selectivity).
  * bfloat16 MFMA operands, float32 accumulation, float32 master weights and
@@ -298,7 +308,10 @@ int esc_mlp_set_params(esc_mlp *m, const float *host_params);   /* also resets A
 int esc_mlp_get_params(esc_mlp *m, float *host_params);
 /* yhat[i] for n rows of dev_x (n x 64 float32, device) into dev_yhat. */
 int esc_mlp_predict(esc_mlp *m, const float *dev_x, int64_t n, float *dev_yhat, void *stream);
-/* Gradient of mean((yhat - y)^2) over the n rows (n <= 4096), written as a
+/* Training loss: mean over rows of the Huber loss of e = yhat - y with
+ * threshold 1/2 (e^2 / 2 for |e| <= 1/2, (|e| - 1/4) / 2 beyond): squared
+ * for small ln-selectivity errors, linear for large ones.
+ * esc_mlp_gradients: its gradient over the n rows (n <= 4096), written as a
  * flat float32 array in the parameter order into dev_grads. */
 int esc_mlp_gradients(esc_mlp *m, const float *dev_x, const float *dev_y, int64_t n,
                       float *dev_grads, void *stream);

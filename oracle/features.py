@@ -7,26 +7,51 @@ Featurization (the learned estimator's input; the paper has no estimator,
 so this is the build's definition).  For each of the first six columns c,
 ten float32 values at offset 10*c:
 
-  [present, lo, hi, is_eq, is_lt, is_gt, is_between, is_in, in_size/16, in_or]
-
-  present     1 if some leaf references column c
-  lo, hi      the constraint the conjunction puts on c, normalised to [0,1]
-              with the catalog minimum and maximum (0 and 1 when free)
-  is_*        1 if some leaf on c uses that comparison
-  in_size     total length of the IN-lists on c, divided by 16
-  in_or       1 if some leaf on c sits under an OR
+  [lsel, lo, hi, is_eq, is_lt, is_gt, is_between, in_mass, in_size/16, in_or]
 
 followed by four global values [n_conj/6, n_or/6, has_udf, n_leaves/16].
+Everything is computed in float64 and rounded to float32 once at the end.
 
-Normalisation of a constant v of column c, every step rounded to float32:
-  d = f32(v) - f32(min_c); s = f32(max_c) - f32(min_c); q = d / s,
-  clamped to [0, 1]; 0 when s == 0 or v is NaN.
-Leaf intervals: eq k -> [k,k]; lt k -> [min, k]; gt k -> [k, max];
-between a b -> [a, b]; in S -> [min S, max S].  A conjunct that is a leaf
-intersects its interval into its column's [lo, hi]; a conjunct that is an
-OR of leaves on one column intersects the union hull of their intervals;
-anything else only sets flags.  Conjuncts are the children of a root AND,
-or the root itself.
+Column CDF.  From the catalog minimum and maximum of the column and a row
+sample (values that are NaN or outside [min, max] are dropped; m = number
+kept), with u_1 < ... < u_k the distinct sampled values:
+  knot u_j carries a left limit  L_j = (#{s < u_j} + 1/2) / m
+                and a right limit R_j = (#{s <= u_j} - 1/2) / m;
+  a knot (min, 0, 0) goes in front unless min == u_1, in which case L_1 = 0;
+  a knot (max, 1, 1) goes behind unless max == u_k, in which case R_k = 1;
+  G(v) = 0 below the first knot, 1 above the last, L_j / R_j at a knot
+  (for "below v" / "at most v"), and between knots a and b the straight line
+  from R_a to L_b.
+F_below(v) and F_atmost(v) are G(v) with the left / right limit for a
+float32 column; an integer column (int32, date32) uses G(v - 1/2) and
+G(v + 1/2).  A NaN constant maps to 0.  With no sample, the knots are just
+(min, 0, 0) and (max, 1, 1): the CDF of a uniform column.
+
+Leaf ranges [a, b]: eq k -> [F_below(k), F_atmost(k)]; lt k -> [0, F_below(k)];
+gt k -> [F_atmost(k), 1]; between x y -> [F_below(x), F_atmost(y)];
+in S -> [F_below(min S), F_atmost(max S)] over the non-NaN constants
+([0, 0] if there are none).
+
+Per column (leaves at any depth): is_eq / is_lt / is_gt / is_between are 1
+if some leaf on the column uses that comparison; every IN leaf adds its
+number of constants / 16 to in_size and, to in_mass, the sum over its
+distinct non-NaN constants v (ascending) of F_atmost(v) - F_below(v).
+The conjuncts are the children of a root AND, or the root itself; the j-th
+conjunct (1-based) that contains an OR marks every leaf inside it with j/4,
+and in_or is the largest mark of the column's leaves.
+
+lo / hi start at 0 / 1 and are intersected with: the range of each leaf
+conjunct; for an OR conjunct whose children are all leaves, the hull (min a,
+max b) of its leaves on each column -- for every column if the OR has one
+column, else only for columns that no leaf conjunct constrains.
+
+lsel: 0 for a column no leaf mentions; otherwise with est = max(hi - lo, 0),
+replaced by in_mass when in_size > 0, in_mass > 0 and in_mass < est,
+lsel = min((0 - ln(max(est, 1e-9))) / 20.72326583694641, 1) (0 - x, not -x,
+so that an unconstrained column gives +0).
+
+Globals: conjunct count / 6, number of OR nodes / 6, 1 if any udf leaf,
+number of leaves / 16.
 """
 from __future__ import annotations
 
@@ -36,89 +61,178 @@ import numpy as np
 
 NFEAT = 64
 NCOLF = 6
-F32 = np.float32
+LEAVES = ("eq", "lt", "gt", "between", "in")
 
 
-def _norm(v, lo, hi):
-    v, lo, hi = F32(v), F32(lo), F32(hi)
-    if np.isnan(v):
-        return F32(0.0)
-    s = F32(hi - lo)
-    if s == 0 or np.isnan(s):
-        return F32(0.0)
-    q = F32(F32(v - lo) / s)
-    return F32(min(max(q, F32(0.0)), F32(1.0)))
+class ColumnCdf:
+    """The smoothed sample CDF of one column (see the module docstring)."""
+
+    def __init__(self, lo, hi, is_int, sample=()):
+        lo, hi = float(lo), float(hi)
+        vals = sorted(float(v) for v in sample if not math.isnan(float(v)) and lo <= float(v) <= hi)
+        m = len(vals)
+        knots = []   # [value, left limit, right limit]
+        i = 0
+        while i < m:
+            j = i
+            while j < m and vals[j] == vals[i]:
+                j += 1
+            knots.append([vals[i], (i + 0.5) / m, (j - 0.5) / m])
+            i = j
+        if not knots or lo < knots[0][0]:
+            knots.insert(0, [lo, 0.0, 0.0])
+        else:
+            knots[0][1] = 0.0
+        if hi > knots[-1][0]:
+            knots.append([hi, 1.0, 1.0])
+        else:
+            knots[-1][2] = 1.0
+        self.knots = knots
+        self.is_int = is_int
+
+    def _g(self, v, atmost):
+        k = self.knots
+        if v < k[0][0]:
+            return 0.0
+        if v > k[-1][0]:
+            return 1.0
+        for idx, (u, left, right) in enumerate(k):
+            if u == v:
+                return right if atmost else left
+            if u > v:
+                pu, _, pright = k[idx - 1]
+                t = (v - pu) / (u - pu)
+                return pright + t * (left - pright)
+        raise AssertionError
+
+    def below(self, v):
+        v = float(v)
+        if math.isnan(v):
+            return 0.0
+        return self._g(v - 0.5, False) if self.is_int else self._g(v, False)
+
+    def atmost(self, v):
+        v = float(v)
+        if math.isnan(v):
+            return 0.0
+        return self._g(v + 0.5, True) if self.is_int else self._g(v, True)
 
 
-def _leaf_interval(leaf, cmin, cmax):
+class Catalog:
+    """Per-column CDFs for the first six columns.  dtypes: 'i' for int32 /
+    date32, 'f' for float32; sample: per column a list of values, or None."""
+
+    def __init__(self, cmin, cmax, dtypes, sample=None):
+        n = min(len(dtypes), NCOLF)
+        self.cdf = [ColumnCdf(cmin[c], cmax[c], dtypes[c] != "f", () if sample is None else sample[c])
+                    for c in range(n)]
+
+
+def _values(leaf):
+    return sorted(set(float(v) for v in leaf[2] if not math.isnan(float(v))))
+
+
+def _range(leaf, cat):
     op, c = leaf[0], leaf[1]
-    n = lambda v: _norm(v, cmin[c], cmax[c])
+    F = cat.cdf[c]
     if op == "eq":
-        return n(leaf[2]), n(leaf[2])
+        return F.below(leaf[2]), F.atmost(leaf[2])
     if op == "lt":
-        return F32(0.0), n(leaf[2])
+        return 0.0, F.below(leaf[2])
     if op == "gt":
-        return n(leaf[2]), F32(1.0)
+        return F.atmost(leaf[2]), 1.0
     if op == "between":
-        return n(leaf[2]), n(leaf[3])
-    vals = [F32(v) if not isinstance(v, (int, np.integer)) else v for v in leaf[2]]
-    return n(min(vals)), n(max(vals))
+        return F.below(leaf[2]), F.atmost(leaf[3])
+    vals = _values(leaf)
+    if not vals:
+        return 0.0, 0.0
+    return F.below(vals[0]), F.atmost(vals[-1])
 
 
-def featurize(pred, cmin, cmax):
-    f = np.zeros(NFEAT, np.float32)
+def _has_or(p):
+    if p[0] == "or":
+        return True
+    return p[0] == "and" and any(_has_or(q) for q in p[1])
+
+
+def featurize(pred, cat):
+    f = [0.0] * NFEAT
     for c in range(NCOLF):
         f[10 * c + 2] = 1.0
-    counts = {"leaves": 0, "or": 0, "udf": 0}
-    opslot = {"eq": 3, "lt": 4, "gt": 5, "between": 6, "in": 7}
+    present = [False] * NCOLF
+    stats = {"leaves": 0, "or": 0, "udf": 0}
+    opslot = {"eq": 3, "lt": 4, "gt": 5, "between": 6}
 
-    def flags(p, under_or):
-        op = p[0]
-        if op in ("and", "or"):
-            if op == "or":
-                counts["or"] += 1
+    def visit(p, mark):
+        if p[0] in ("and", "or"):
+            if p[0] == "or":
+                stats["or"] += 1
             for q in p[1]:
-                flags(q, under_or or op == "or")
+                visit(q, mark)
             return
-        counts["leaves"] += 1
-        if op == "udf":
-            counts["udf"] = 1
+        stats["leaves"] += 1
+        if p[0] == "udf":
+            stats["udf"] = 1
             return
         c = p[1]
         if c >= NCOLF:
             return
-        f[10 * c] = 1.0
-        f[10 * c + opslot[op]] = 1.0
-        if op == "in":
-            f[10 * c + 8] = F32(f[10 * c + 8] + F32(len(p[2])) / F32(16.0))
-        if under_or:
-            f[10 * c + 9] = 1.0
+        present[c] = True
+        if p[0] == "in":
+            F = cat.cdf[c]
+            mass = 0.0
+            for v in _values(p):
+                mass += F.atmost(v) - F.below(v)
+            f[10 * c + 7] += mass
+            f[10 * c + 8] += len(p[2]) / 16.0
+        else:
+            f[10 * c + opslot[p[0]]] = 1.0
+        f[10 * c + 9] = max(f[10 * c + 9], mark)
 
-    def clamp(c, lo, hi):
-        if c >= NCOLF:
-            return
-        f[10 * c + 1] = max(f[10 * c + 1], lo)
-        f[10 * c + 2] = min(f[10 * c + 2], hi)
-
-    flags(pred, False)
     conj = pred[1] if pred[0] == "and" else [pred]
+    j = 0
     for q in conj:
-        if q[0] in ("eq", "lt", "gt", "between", "in"):
-            lo, hi = _leaf_interval(q, cmin, cmax)
-            clamp(q[1], lo, hi)
-        elif q[0] == "or" and all(k[0] in ("eq", "lt", "gt", "between", "in") for k in q[1]) \
-                and len({k[1] for k in q[1]}) == 1:
-            iv = [_leaf_interval(k, cmin, cmax) for k in q[1]]
-            clamp(q[1][0][1], min(a for a, _ in iv), max(b for _, b in iv))
-    f[60] = F32(len(conj)) / F32(6.0)
-    f[61] = F32(counts["or"]) / F32(6.0)
-    f[62] = F32(counts["udf"])
-    f[63] = F32(counts["leaves"]) / F32(16.0)
-    return f
+        mark = 0.0
+        if _has_or(q):
+            j += 1
+            mark = j / 4.0
+        visit(q, mark)
+
+    def narrow(c, a, b):
+        f[10 * c + 1] = max(f[10 * c + 1], a)
+        f[10 * c + 2] = min(f[10 * c + 2], b)
+
+    bound_by_leaf = {q[1] for q in conj if q[0] in LEAVES}
+    for q in conj:
+        if q[0] in LEAVES:
+            if q[1] < NCOLF:
+                narrow(q[1], *_range(q, cat))
+        elif q[0] == "or" and all(k[0] in LEAVES for k in q[1]):
+            cols = []
+            for k in q[1]:
+                if k[1] not in cols:
+                    cols.append(k[1])
+            for c in cols:
+                if c >= NCOLF or (len(cols) > 1 and c in bound_by_leaf):
+                    continue
+                rs = [_range(k, cat) for k in q[1] if k[1] == c]
+                narrow(c, min(a for a, _ in rs), max(b for _, b in rs))
+    for c in range(NCOLF):
+        if not present[c]:
+            continue
+        est = max(f[10 * c + 2] - f[10 * c + 1], 0.0)
+        if f[10 * c + 8] > 0.0 and 0.0 < f[10 * c + 7] < est:
+            est = f[10 * c + 7]
+        f[10 * c] = min((0.0 - math.log(max(est, 1e-9))) / 20.72326583694641, 1.0)
+    f[60] = len(conj) / 6.0
+    f[61] = stats["or"] / 6.0
+    f[62] = float(stats["udf"])
+    f[63] = stats["leaves"] / 16.0
+    return np.array(f, dtype=np.float32)
 
 
-def featurize_many(preds, cmin, cmax):
-    return np.stack([featurize(p, cmin, cmax) for p in preds]) if preds else np.zeros((0, NFEAT), np.float32)
+def featurize_many(preds, cat):
+    return np.stack([featurize(p, cat) for p in preds]) if preds else np.zeros((0, NFEAT), np.float32)
 
 
 # ------------------------------------------------------------------ gate

@@ -13,7 +13,9 @@ this build's extension, so its definition is the one written out here:
             (round-to-nearest-even): the input X, the weights, the hidden
             activations handed to the next layer, and the back-propagated
             deltas handed to a product; sums are exact in float64 here;
-  loss      L = mean_b (yhat_b - y_b)^2;
+  loss      L = mean_b h(yhat_b - y_b), the Huber loss with threshold
+            d = 1/2: h(e) = e^2 / 2 for |e| <= d, d (|e| - d / 2) beyond
+            (its derivative is e clamped to [-d, d]);
   backward  chain rule; the ReLU derivative is 1 where the (rounded)
             activation is > 0 and 0 elsewhere (0 at exactly 0); bias
             gradients sum the un-rounded deltas;
@@ -62,15 +64,20 @@ def forward(params, x, rounding=True):
     raise AssertionError
 
 
+HUBER = 0.5
+
+
 def loss(yhat, y):
-    return float(np.mean((yhat - np.asarray(y, np.float64)) ** 2))
+    e = np.asarray(yhat, np.float64) - np.asarray(y, np.float64)
+    a = np.abs(e)
+    return float(np.mean(np.where(a <= HUBER, 0.5 * e * e, HUBER * (a - 0.5 * HUBER))))
 
 
 def backward(params, acts, yhat, y, rounding=True):
-    """Gradients [(dW1, db1), ...] of the mean squared error."""
+    """Gradients [(dW1, db1), ...] of the mean Huber loss."""
     r = bf16 if rounding else _id
     bsz = len(y)
-    d = (2.0 / bsz) * (yhat - np.asarray(y, np.float64))      # dL/dyhat, shape [B]
+    d = np.clip(yhat - np.asarray(y, np.float64), -HUBER, HUBER) / bsz   # dL/dyhat, shape [B]
     grads = [None] * len(params)
     # output layer: yhat = a3 . w4 + b4
     w4 = params[-1][0]

@@ -35,6 +35,7 @@ namespace esc {
 
 constexpr int kIn = 64, kHid = 256;
 constexpr int kMaxRows = 4096;   // rows per forward / gradient pass
+constexpr float kHuber = 0.5f;   // Huber loss threshold on ln(selectivity) errors
 
 // flat parameter layout (float32): W1, b1, W2, b2, W3, b3, W4, b4
 constexpr int kOffW1 = 0;
@@ -163,9 +164,11 @@ __global__ void gather_round_kernel(const float *X, const float *Y, const int32_
 }
 
 // One wave per row: y = a3 . bf16(W4) + b4; with targets, also the start of
-// the backward pass: dy = 2 (y - t) / rows, dz3 = dy * bf16(W4) * (a3 > 0).
+// the backward pass for the Huber loss of e = y - t (e^2 / 2 for |e| <= kHuber,
+// kHuber (|e| - kHuber / 2) beyond): dy = clamp(e, -kHuber, kHuber) / rows,
+// dz3 = dy * bf16(W4) * (a3 > 0).
 __global__ void head_kernel(const bf16_t *a3, const bf16_t *w4b, const float *b4, int rows, float *yhat,
-                            const float *tgt, float *dy, float *sqerr, float *dz3, bf16_t *g3)
+                            const float *tgt, float *dy, float *rloss, float *dz3, bf16_t *g3)
 {
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -185,10 +188,11 @@ __global__ void head_kernel(const bf16_t *a3, const bf16_t *w4b, const float *b4
     if (lane == 0 && yhat) yhat[r] = y;
     if (!tgt) return;
     const float e = y - tgt[r];
-    const float d = 2.0f * e / (float)rows;
+    const float ae = fabsf(e);
+    const float d = fminf(fmaxf(e, -kHuber), kHuber) / (float)rows;
     if (lane == 0) {
         dy[r] = d;
-        sqerr[r] = e * e;
+        rloss[r] = ae <= kHuber ? 0.5f * e * e : kHuber * (ae - 0.5f * kHuber);
     }
 #pragma unroll
     for (int j = 0; j < 4; j++) {
@@ -210,8 +214,8 @@ __global__ void colsum_kernel(const float *src, int rows, int cols, float *out)
     out[n] = s;
 }
 
-// gW4[k] = sum_r a3[r][k] dy[r]; gb4 = sum_r dy[r]; loss = sum_r sqerr[r] / rows
-__global__ void head_reduce_kernel(const bf16_t *a3, const float *dy, const float *sqerr, int rows, float *gw4,
+// gW4[k] = sum_r a3[r][k] dy[r]; gb4 = sum_r dy[r]; loss = sum_r rloss[r] / rows
+__global__ void head_reduce_kernel(const bf16_t *a3, const float *dy, const float *rloss, int rows, float *gw4,
                                    float *gb4, float *loss_buf, const long long *step)
 {
     const int k = threadIdx.x;
@@ -220,7 +224,7 @@ __global__ void head_reduce_kernel(const bf16_t *a3, const float *dy, const floa
     gw4[k] = s;
     if (k == 0) {
         float d = 0.0f, q = 0.0f;
-        for (int r = 0; r < rows; r++) { d += dy[r]; q += sqerr[r]; }
+        for (int r = 0; r < rows; r++) { d += dy[r]; q += rloss[r]; }
         gb4[0] = d;
         if (loss_buf) loss_buf[step ? *step : 0] = q / (float)rows;
     }

@@ -68,7 +68,7 @@ class BatchOpts(ctypes.Structure):
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-ABI_VERSION = 3   # esc.h's ESC_ABI_VERSION for the struct layouts below
+ABI_VERSION = 4   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -107,7 +107,7 @@ def lib():
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
             "esc_batch_destroy": ([vp], ctypes.c_int),
-            "esc_featurize": ([vp, vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_featurize": ([vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_mlp_create": ([vp, P(vp)], ctypes.c_int),
             "esc_mlp_destroy": ([vp], ctypes.c_int),
             "esc_mlp_set_params": ([vp, vp], ctypes.c_int),
@@ -413,19 +413,37 @@ class Batch:
 
 # ------------------------------------------------------------------ learned gate
 
-def featurize(schema: Table, preds, cmin, cmax):
-    """64 float32 features per compiled predicate (host, in the library)."""
+def featurize(schema: Table, preds, cmin, cmax, sample=None):
+    """64 float32 features per compiled predicate (host, in the library).
+    sample: per column c < min(ncols, 6), the same number of row values (or
+    None: no sample)."""
+    nc = min(len(schema.dtypes), 6)
     vmin = (Value * len(schema.dtypes))()
     vmax = (Value * len(schema.dtypes))()
+
+    def put(arr, i, dt, v):
+        if dt == FLOAT32:
+            arr[i].f = float(np.float32(v))
+        else:
+            arr[i].i = int(v)
+
     for c, dt in enumerate(schema.dtypes):
-        for arr, v in ((vmin, cmin[c]), (vmax, cmax[c])):
-            if dt == FLOAT32:
-                arr[c].f = float(np.float32(v))
-            else:
-                arr[c].i = int(v)
+        put(vmin, c, dt, cmin[c])
+        put(vmax, c, dt, cmax[c])
+    m = 0 if sample is None else len(sample[0])
+    vs = (Value * max(nc * m, 1))()
+    for c in range(nc if m else 0):
+        col = np.asarray(sample[c])
+        if len(col) != m:
+            raise ValueError("every column sample needs the same length")
+        if schema.dtypes[c] == FLOAT32:
+            bits = col.astype(np.float32).view(np.uint32)
+        else:
+            bits = col.astype(np.int64).astype(np.int32).view(np.uint32)
+        ctypes.memmove(ctypes.addressof(vs) + c * m * 4, bits.ctypes.data, m * 4)
     ph = (ctypes.c_void_p * max(len(preds), 1))(*[p.h for p in preds])
     out = np.zeros((len(preds), 64), np.float32)
-    check(lib().esc_featurize(schema.h, vmin, vmax, ph, len(preds), out.ctypes.data))
+    check(lib().esc_featurize(schema.h, vmin, vmax, vs, m, ph, len(preds), out.ctypes.data))
     return out
 
 

@@ -50,17 +50,47 @@ def c_hat(yhat, n):
     return np.clip(float(n) * np.exp(np.asarray(yhat, np.float64)), 1.0, float(n))
 
 
+class Catalog:
+    """Column statistics the featurization reads: minimum, maximum and a
+    uniform row sample (the same rows for every column) of the first six
+    columns, as host values."""
+
+    SAMPLE_ROWS = 4096
+
+    def __init__(self, cmin, cmax, sample=None):
+        self.cmin, self.cmax, self.sample = list(cmin), list(cmax), sample
+
+    @classmethod
+    def of(cls, table, rows=SAMPLE_ROWS, seed=0):
+        """From a datagen table whose columns are numpy arrays or device
+        tensors."""
+        cols = table.cols
+        n = table.nrows
+        idx = np.random.default_rng(seed).integers(0, max(n, 1), rows if n else 0)
+        if cols and not isinstance(cols[0], np.ndarray):   # device tensors
+            import torch
+            ti = torch.from_numpy(idx).to(cols[0].device)
+            cmin = [c.min().item() for c in cols]
+            cmax = [c.max().item() for c in cols]
+            sample = [c[ti].cpu().numpy() for c in cols[:6]]
+        else:
+            cmin = [c.min() for c in cols]
+            cmax = [c.max() for c in cols]
+            sample = [np.asarray(c)[idx] for c in cols[:6]]
+        return cls(cmin, cmax, sample if n else None)
+
+
 class Estimator:
     """Featurization + MLP for one table."""
 
-    def __init__(self, ctx, schema: esc.Table, cmin, cmax, params):
-        self.ctx, self.schema = ctx, schema
-        self.cmin, self.cmax = cmin, cmax
+    def __init__(self, ctx, schema: esc.Table, catalog: Catalog, params):
+        self.ctx, self.schema, self.catalog = ctx, schema, catalog
         self.mlp = esc.MLP(ctx, params)
         self.nrows = schema.nrows
 
     def features(self, preds):
-        return esc.featurize(self.schema, preds, self.cmin, self.cmax)
+        c = self.catalog
+        return esc.featurize(self.schema, preds, c.cmin, c.cmax, c.sample)
 
     def train(self, x, y, epochs, batch, lr, order_seed):
         import torch

@@ -3,34 +3,51 @@ oracle: features must match bit for bit, routing decisions exactly."""
 import math
 
 import numpy as np
+import pytest
 
 from oracle import features as fo
 from paper_1901_01488_amd import datagen as dg
-from paper_1901_01488_amd import esc
+from paper_1901_01488_amd import esc, learned
 
 
-def test_featurize_matches_oracle_bitwise():
+def _oracle_catalog(t, cat):
+    return fo.Catalog(cat.cmin, cat.cmax, ["f" if d == dg.FLOAT32 else "i" for d in t.dtypes], cat.sample)
+
+
+@pytest.mark.parametrize("rows", [0, 1, 7, 4096])
+def test_featurize_matches_oracle_bitwise(rows):
     t = dg.table_mixed(50_000, 6, seed=3, kinds=dg.LEARNED_KINDS)
-    cmin = [c.min() for c in t.cols]
-    cmax = [c.max() for c in t.cols]
+    cat = learned.Catalog.of(t, rows=rows, seed=rows) if rows else learned.Catalog.of(t, rows=1, seed=0)
+    if not rows:
+        cat.sample = None
     schema = esc.schema_table(t)
-    preds = dg.preds_mixed(t, 300, seed=4)
+    preds = dg.preds_mixed(t, 200, seed=4) + dg.preds_anchored(t, 200, seed=5)
     cps = [esc.Pred(schema, p) for p in preds]
-    got = esc.featurize(schema, cps, cmin, cmax)
-    want = fo.featurize_many(preds, cmin, cmax)
-    assert got.shape == want.shape == (300, 64)
+    got = esc.featurize(schema, cps, cat.cmin, cat.cmax, cat.sample)
+    want = fo.featurize_many(preds, _oracle_catalog(t, cat))
+    assert got.shape == want.shape == (400, 64)
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
 def test_featurize_golden_cases_through_library():
-    from test_oracle_mlp import _read_feature_golden
+    from test_oracle_mlp import GOLDEN_DTYPES, GOLDEN_MAX, GOLDEN_MIN, _read_feature_golden, golden_sample
     schema = esc.Table(10, [dg.INT32, dg.INT32, dg.INT32, dg.INT32, dg.INT32, dg.FLOAT32])
-    cmin = [0, 0, 0, 0, 0, np.float32(1.0)]
-    cmax = [100, 9, 1000, 1, 0, np.float32(3.0)]
     for case in _read_feature_golden():
-        got = esc.featurize(schema, [esc.Pred(schema, case["pred"])], cmin, cmax)[0]
-        want = fo.featurize(case["pred"], cmin, cmax)
-        assert np.array_equal(got, want), case["pred"]
+        smp = golden_sample(case)
+        got = esc.featurize(schema, [esc.Pred(schema, case["pred"])], GOLDEN_MIN, GOLDEN_MAX, smp)[0]
+        want = fo.featurize(case["pred"], fo.Catalog(GOLDEN_MIN, GOLDEN_MAX, GOLDEN_DTYPES, smp))
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), case["pred"]
+
+
+def test_featurize_errors():
+    schema = esc.Table(10, [dg.INT32, dg.FLOAT32])
+    p = esc.Pred(schema, ("eq", 0, 1))
+    with pytest.raises(esc.EscError):
+        esc.featurize(schema, [p], [5, np.float32(0)], [1, np.float32(1)])          # min above max
+    with pytest.raises(esc.EscError):
+        esc.featurize(schema, [p], [0, np.float32(np.nan)], [1, np.float32(1)])     # NaN bound
+    with pytest.raises(ValueError):
+        esc.featurize(schema, [p], [0, np.float32(0)], [1, np.float32(1)], [[0, 1], [0.5]])
 
 
 def test_gate_matches_oracle():

@@ -32,9 +32,7 @@ def test_planning_gate_gain(ctx):
         specs = dg.preds_mixed(t, 8192, seed=dg.pred_seed(4) + 100 + i, min_conj=2, max_conj=6)
         cps = [esc.Pred(dt, p) for p in specs]
         cnt = learned.exact_counts(ctx, dt, cps)
-        host_min = [int(c.min().item()) for c in t.cols]
-        host_max = [int(c.max().item()) for c in t.cols]
-        e = learned.Estimator(ctx, dt, host_min, host_max, dg.mlp_init(dg.MLP_SEED))
+        e = learned.Estimator(ctx, dt, learned.Catalog.of(t, seed=9 + i), dg.mlp_init(dg.MLP_SEED))
         x = e.features(cps)
         e.train(x, learned.labels(cnt, t.nrows), epochs=15, batch=1024, lr=2e-3, order_seed=9 + i)
         ests.append(e)

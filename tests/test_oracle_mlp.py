@@ -130,16 +130,29 @@ def test_q_error_and_label():
 
 # ----------------------------------------------------------- featurization
 
+GOLDEN_MIN = [0, 0, 0, 0, 0, np.float32(1.0)]
+GOLDEN_MAX = [100, 9, 1000, 1, 0, np.float32(3.0)]
+GOLDEN_DTYPES = "iiiiif"
+
+
 def _read_feature_golden():
+    """Cases of tests/golden/features.txt: {"pred", "sample", "nz"}."""
     cases = []
+    sample = None
     with open(os.path.join(GOLDEN, "features.txt")) as f:
         cur = None
         for line in f:
             line = line.split("#", 1)[0].strip()
             if not line:
                 continue
-            if line.startswith("pred "):
-                cur = {"pred": eval(line[5:], {"np": np}), "nz": {}}   # fixture literal, written by hand
+            if line == "sample none":
+                sample = None
+            elif line.startswith("sample "):
+                c, vals = line[7:].split(":")
+                sample = dict(sample or {})
+                sample[int(c)] = [float(v) if GOLDEN_DTYPES[int(c)] == "f" else int(v) for v in vals.split()]
+            elif line.startswith("pred "):
+                cur = {"pred": eval(line[5:], {"np": np}), "nz": {}, "sample": sample}   # fixture literal, written by hand
                 cases.append(cur)
             else:
                 k, v = line.split("=")
@@ -147,17 +160,44 @@ def _read_feature_golden():
     return cases
 
 
+def golden_sample(case):
+    s = case["sample"]
+    return None if s is None else [s[c] for c in range(6)]
+
+
 def test_featurize_golden():
-    cmin = [0, 0, 0, 0, 0, np.float32(1.0)]
-    cmax = [100, 9, 1000, 1, 0, np.float32(3.0)]
     for case in _read_feature_golden():
-        f = fo.featurize(case["pred"], cmin, cmax)
+        cat = fo.Catalog(GOLDEN_MIN, GOLDEN_MAX, GOLDEN_DTYPES, golden_sample(case))
+        f = fo.featurize(case["pred"], cat)
         want = np.zeros(64, np.float32)
         for c in range(6):
             want[10 * c + 2] = 1.0
         for k, v in case["nz"].items():
             want[k] = np.float32(v)
         assert np.array_equal(f, want), (case["pred"], np.flatnonzero(f != want), f[f != want])
+
+
+def test_column_cdf_properties():
+    """The smoothed CDF is monotone, 0 below the minimum and 1 above the
+    maximum, and the mass of an integer column's cells sums to 1."""
+    rng = np.random.default_rng(8)
+    for _ in range(20):
+        smp = rng.zipf(1.3, 300) % 50
+        cdf = fo.ColumnCdf(0, 60, True, smp)
+        cells = [cdf.atmost(k) - cdf.below(k) for k in range(0, 61)]
+        assert all(c >= 0 for c in cells)
+        assert abs(sum(cells) - 1.0) < 1e-12
+        vals = [cdf.atmost(k) for k in range(-3, 64)]
+        assert all(a <= b for a, b in zip(vals, vals[1:]))
+        assert cdf.below(0) == 0.0 and cdf.atmost(60) == 1.0
+        # a value sampled r times carries a jump of (r - 1) / m plus its cell
+        v = int(np.bincount(smp).argmax())
+        r = int((smp == v).sum())
+        assert cdf.atmost(v) - cdf.below(v) >= (r - 1) / len(smp) - 1e-12
+    f = fo.ColumnCdf(-1.0, 1.0, False, rng.standard_normal(500).clip(-1, 1))
+    xs = np.linspace(-1.5, 1.5, 301)
+    ys = [f.atmost(x) for x in xs]
+    assert all(a <= b for a, b in zip(ys, ys[1:])) and ys[0] == 0.0 and ys[-1] == 1.0
 
 
 # ----------------------------------------------------------- gate
@@ -185,3 +225,11 @@ def test_gate_join_pair():
     assert fo.route_join_pair(yr, 10**7, ys, 10**8, beta)
     ys2 = math.log(3000 / 10**8)     # ratio 1/3 < 0.444 -> order is safe
     assert not fo.route_join_pair(yr, 10**7, ys2, 10**8, beta)
+
+
+def test_huber_loss_values():
+    # e^2 / 2 inside the threshold 1/2, 1/2 (|e| - 1/4) beyond; continuous at |e| = 1/2
+    assert mlp.loss(np.array([0.25]), np.array([0.0])) == 0.03125
+    assert mlp.loss(np.array([-2.0]), np.array([0.0])) == 0.875
+    assert mlp.loss(np.array([0.5]), np.array([0.0])) == 0.125
+    assert mlp.loss(np.array([3.0, 1.0]), np.array([3.0, 0.75])) == 0.015625
