@@ -169,8 +169,9 @@ typedef struct {
     int32_t ncols;        /* distinct columns read by a scan */
     int32_t constant;     /* 0: data-dependent; 1: always true; -1: always false */
     uint64_t col_mask;    /* bit c set when column c is read (c < 64) */
-    int32_t nhashed;      /* IN-lists tested by a 64-slot table lookup instead of
-                             one compare per constant */
+    int32_t nhashed;      /* IN-lists tested by one table lookup (64-slot key
+                             table or 2048-bit bitmap) instead of one compare
+                             per constant */
     int32_t pad;
 } esc_pred_info;
 int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);

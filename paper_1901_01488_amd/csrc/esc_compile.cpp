@@ -9,8 +9,9 @@
 //      64-value bitmap, or a set), folding leaves whose value does not
 //      depend on the row (always true / always false); sets of three or
 //      more keys become slot tables when a 6-bit field of the value
-//      separates the keys (one cross-lane read per row instead of one
-//      compare per key);
+//      separates the keys, else 2048-bit bitmaps when the int keys span
+//      less than 2048 (one cross-lane read per row instead of one compare
+//      per key);
 //   3. convert to an AND of OR-clauses by distributing OR over AND -- exact
 //      because the language has no negation;
 //   4. give each referenced column a register slot and emit instructions.
@@ -462,6 +463,7 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     for (int li : in_leaves) need += (int)C.leaves[li].kvals.size();
     if (need > kMaxKpool) return fail(ESC_ERR_UNSUPPORTED, "predicate has more than %d IN constants", kMaxKpool);
     std::vector<int> rot_of(C.leaves.size(), -1), table_of(C.leaves.size(), -1);
+    std::vector<int32_t> bitmap_lo(C.leaves.size(), 0);
     int ntables = 0;
     {
         const int hmin = in_hash_min();
@@ -474,13 +476,25 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
             if (hmin <= 0 || n < hmin || need + (kSlotTable - n) > kMaxKpool) continue;
             const std::vector<uint32_t> keys = slot_keys(L);
             const int rot = slot_rotation(keys);
-            if (rot < 0) continue;
-            rot_of[li] = rot;
-            table_of[li] = ntables;
-            // every entry holds some key, so an entry equal to x means x is a key
             uint32_t *tab = P.kpool + kSlotTable * ntables;
-            for (int e = 0; e < kSlotTable; e++) tab[e] = keys[0];
-            for (uint32_t k : keys) tab[slot_of_key(k, rot)] = k;
+            if (rot >= 0) {
+                // every entry holds some key, so an entry equal to x means x is a key
+                rot_of[li] = rot;
+                for (int e = 0; e < kSlotTable; e++) tab[e] = keys[0];
+                for (uint32_t k : keys) tab[slot_of_key(k, rot)] = k;
+            } else if (L.test.op == T_IN_I32 &&
+                       (int64_t)(int32_t)L.kvals.back() - (int32_t)L.kvals.front() < 32 * kSlotTable) {
+                // int keys within 2048 of the smallest: a bitmap, 32 bits per entry
+                bitmap_lo[li] = (int32_t)L.kvals.front();
+                for (int e = 0; e < kSlotTable; e++) tab[e] = 0u;
+                for (uint32_t k : L.kvals) {
+                    const uint32_t d = k - (uint32_t)bitmap_lo[li];
+                    tab[d >> 5] |= 1u << (d & 31u);
+                }
+            } else {
+                continue;
+            }
+            table_of[li] = ntables;
             ntables++;
             need += kSlotTable - n;
         }
@@ -509,9 +523,9 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
             Insn t = L.test;
             if (!L.udf) t.src = (uint8_t)slot_of[t.src];
             if (table_of[li] >= 0) {
-                t.op = T_IN_HASH;
+                t.op = rot_of[li] >= 0 ? T_IN_HASH : T_IN_BITMAP;
                 t.a = kSlotTable * table_of[li];
-                t.b = rot_of[li];
+                t.b = rot_of[li] >= 0 ? rot_of[li] : bitmap_lo[li];
                 t.c = table_of[li];
             } else if (t.op == T_IN_I32 || t.op == T_IN_F32) {
                 if (kpool_at[li] < 0) {

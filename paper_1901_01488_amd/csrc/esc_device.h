@@ -93,11 +93,12 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
         return bits_of<RPT>([&](int r) { const float f = as_f(x[r]); return lo <= f && f <= hi; });
     }
     case T_BITSET: {
-        const uint32_t lo = (uint32_t)I.a;
-        const uint64_t bits = (uint64_t)(uint32_t)I.b | ((uint64_t)(uint32_t)I.c << 32);
+        // two 32-bit words rather than one 64-bit shift per row
+        const uint32_t lo = (uint32_t)I.a, w0 = (uint32_t)I.b, w1 = (uint32_t)I.c;
         return bits_of<RPT>([&](int r) {
             const uint32_t d = x[r] - lo;
-            return d < 64u && ((bits >> (d & 63u)) & 1ull);
+            const uint32_t w = d < 32u ? w0 : w1;
+            return d < 64u && ((w >> (d & 31u)) & 1u);
         });
     }
     case T_IN_I32: {
@@ -115,6 +116,23 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
             m |= bits_of<RPT>([&](int r) { return as_f(x[r]) == kf; });
         }
         return m;
+    }
+    case T_IN_BITMAP: {
+        // word d >> 5 of the bitmap comes from lane d >> 5 (byte address
+        // (d >> 3) & 0xfc; rows with d >= 2048 read some word and fail the
+        // range test)
+        uint32_t entry;
+        if constexpr (NT > 0) {
+            entry = I.c == 0 ? tabs.e0 : I.c == 1 ? tabs.e1 : I.c == 2 ? tabs.e2 : tabs.e3;
+        } else {
+            entry = kpool[I.a + (threadIdx.x & 63u)];
+        }
+        const uint32_t lo = (uint32_t)I.b;
+        return bits_of<RPT>([&](int r) {
+            const uint32_t d = x[r] - lo;
+            const uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((d >> 3) & 0xfcu), (int)entry);
+            return d < 2048u && ((w >> (d & 31u)) & 1u);
+        });
     }
     case T_IN_HASH: {
         // Lane l holds table entry l; each row reads the entry of its slot

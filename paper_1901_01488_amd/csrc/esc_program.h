@@ -31,6 +31,8 @@ enum Op : uint8_t {
                        // 64-entry slot table whose keys occupy distinct slots (float
                        // lists hold both zeros and no NaN, so bit equality is float
                        // equality); table c of the program, a = 64 * c
+    T_IN_BITMAP = 6,   // d = (uint32)(x - b); d < 2048 && bit (d & 31) of kpool[a + (d >> 5)]:
+                       // a 64-word bitmap of int keys; table c, a = 64 * c
     // udf accumulator updates: operand = slot `src`, or constant a (F_CONST)
     U_LOAD = 16, U_ADD, U_SUB, U_MUL, U_MOD, U_AND, U_OR, U_XOR, U_SHL, U_SHR,
 };

@@ -202,6 +202,11 @@ def test_in_slot_tables(schema, monkeypatch):
     # 0, 1 and 65536: every cyclic 6-bit field misses bit 0 or bit 16, so one
     # pair of keys always shares a slot
     assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 0
+    # no field separates 0, 2, 66, 130 (they need bits 1, 6 and 7), but they
+    # span less than 2048: a bitmap
+    assert info(("in", 0, [0, 2, 66, 130]))["nhashed"] == 1
+    assert info(("in", 0, [0, 2, 66, 130, 2047]))["nhashed"] == 1
+    assert info(("in", 0, [0, 2, 66, 130, 2048]))["nhashed"] == 0
     # float lists: a zero constant needs both zero patterns (two slots)
     assert info(("in", 2, [np.float32(v) for v in (0.0, 2.5, -7.0)]))["nhashed"] == 1
     # pool budget (256 constants): 64 + 4 * 3 as lists leave 180, and each

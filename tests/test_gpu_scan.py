@@ -386,3 +386,44 @@ def test_in_slot_tables(ctx, monkeypatch):
         cp = esc.Pred(dt, p)
         assert cp.info()["nhashed"] == 0
         assert ctx.count(dt, cp) == scan.count(t, p), p
+
+
+def test_in_bitmaps(ctx, monkeypatch):
+    """Int IN-lists that no slot field separates but that span less than
+    2048 are bitmap lookups: exact at the bitmap's edges (d = 0, 2047, 2048
+    and wrap-around below the smallest key), on udf values, and equal to the
+    compare-list form."""
+    rng = np.random.default_rng(77)
+    n = 300_007
+    base = 4096   # keys base + {0, 2, 66, 130}: no 6-bit field separates them
+    vals = np.concatenate([np.arange(base - 40, base + 2100, dtype=np.int64),
+                           [-2**31, 2**31 - 1, base - 1, base + 2047, base + 2048, base + 4096]])
+    col = rng.choice(vals, n).astype(np.int32)
+    other = rng.integers(-5, 5, n).astype(np.int32)
+    t = dg.Table("bitmaps", n, [dg.INT32, dg.INT32], [col, other], ["u", "u"], [None, None])
+    dt = esc.device_table(t)
+    preds = [("in", 0, [base, base + 2, base + 66, base + 130]),
+             ("in", 0, [base, base + 2, base + 66, base + 130, base + 2047]),
+             ("in", 0, [base, base + 2, base + 66, base + 130, base + 2048]),    # too wide: compare list
+             ("in", 0, [int(v) for v in base + np.unique(rng.integers(0, 2048, 200))[:64]]),
+             ("in", 0, [-2**31, -2**31 + 2, -2**31 + 66, -2**31 + 130]),
+             ("in", 0, [2**31 - 131, 2**31 - 129, 2**31 - 65, 2**31 - 1]),
+             ("and", [("in", 0, [base + 1, base + 3, base + 67, base + 131]), ("gt", 1, -2)]),
+             ("udf", ("add", ("col", 0), ("col", 1)), ("in", [base, base + 2, base + 66, base + 130])),
+             ("or", [("in", 0, [base + 5, base + 7, base + 71, base + 135]), ("in", 0, [0, 2, 66, 130])])]
+    tables = 0
+    for p in preds:
+        want = scan.count(t, p)
+        cp = esc.Pred(dt, p)
+        tables += cp.info()["nhashed"]
+        assert ctx.count(dt, cp) == want, p
+        n_gpu, c, ids, outs = gpu_materialize(ctx, dt, p, [0])
+        wc, wids, wouts = scan.materialize(t, p, [0])
+        assert n_gpu == c == wc == want, p
+        assert_same_rows(ids, outs, wids, wouts)
+    assert tables >= len(preds) - 1
+    monkeypatch.setenv("ESC_IN_HASH_MIN", "0")
+    for p in preds:
+        cp = esc.Pred(dt, p)
+        assert cp.info()["nhashed"] == 0
+        assert ctx.count(dt, cp) == scan.count(t, p), p
