@@ -149,7 +149,7 @@ int esc_ctx_create(int device, esc_ctx **out)
         return hip_fail(e, "hipHostMalloc");
     }
     const char *r = getenv("ESC_COUNT_VARIANT");
-    if (r && atoi(r) >= 0 && atoi(r) <= 4) c->count_variant = atoi(r);
+    if (r && atoi(r) >= 0 && atoi(r) <= 2) c->count_variant = atoi(r);
     r = getenv("ESC_NONTEMPORAL");
     if (r) c->nt = atoi(r) != 0;
     r = getenv("ESC_BLOCKS_PER_CU");

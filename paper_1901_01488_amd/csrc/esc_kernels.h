@@ -48,7 +48,6 @@ typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjA
 
 CountFn count_fn(int nslots, int variant, bool udf);
 int count_rpt(int variant, int nslots);
-int count_tpi(int variant, int nslots);
 WriteFn write_fn(int rpt);
 typedef void (*ConjFn)(const Program *, int, const ColPtrs, int64_t, unsigned long long *);
 ConjFn conj_fn(int nslots, bool udf);

@@ -39,10 +39,8 @@ namespace esc {
 
 // Grid-stride over wave tiles.  When to.counts is not null, every wave tile's
 // count and lane masks are stored there.  UDF = false for programs without
-// udf instructions.  TPI > 1 loads the wave's next TPI tiles (tiles t,
-// t + step, ...) before evaluating any of them, so that a program of one or
-// two columns keeps as many bytes in flight per wave as one of four.
-template <int K, int RPT, bool UDF, int TPI = 1>
+// udf instructions.
+template <int K, int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            WsHeader *ws, unsigned long long *out, const TileOut to)
 {
@@ -54,7 +52,10 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
     const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
     uint32_t cnt = 0;   // per lane
-    auto tile_done = [&](int64_t t, uint32_t bits) {
+    for (int64_t t = first; t < ntiles; t += step) {
+        uint32_t v[KK][RPT];
+        load_vals<K, RPT>(cp, t * TILE, n, v);
+        const uint32_t bits = run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(t * TILE, n), tabs);
         const uint32_t c = (uint32_t)__popc(bits);
         if (to.counts) {
             const uint32_t w = wave_sum(c);
@@ -62,24 +63,6 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
             to.bits[t * kWave + lane_id()] = bits;
         }
         cnt += c;
-    };
-    int64_t t = first;
-    if constexpr (TPI > 1) {
-        for (; t + (TPI - 1) * step < ntiles; t += TPI * step) {
-            uint32_t v[TPI][KK][RPT];
-#pragma unroll
-            for (int u = 0; u < TPI; u++) load_vals<K, RPT>(cp, (t + u * step) * TILE, n, v[u]);
-#pragma unroll
-            for (int u = 0; u < TPI; u++) {
-                const int64_t tu = t + u * step;
-                tile_done(tu, run_program<K, RPT, UDF, kMaxTables>(P, v[u], valid_bits<RPT>(tu * TILE, n), tabs));
-            }
-        }
-    }
-    for (; t < ntiles; t += step) {
-        uint32_t v[KK][RPT];
-        load_vals<K, RPT>(cp, t * TILE, n, v);
-        tile_done(t, run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(t * TILE, n), tabs));
     }
     cnt = wave_sum(cnt);
     __shared__ uint32_t s_cnt[NW];
@@ -326,35 +309,16 @@ constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 
 // variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
 // up to four column slots, 16 above (32 rows of five or more columns no
-// longer fit the register file); variant 2: 8 rows per lane; variant 3:
-// variant 1 with four tiles per load round for one column and two for two;
-// variant 4: variant 3 with two tiles per round for three columns too.
+// longer fit the register file); variant 2: 8 rows per lane.
 int count_rpt(int variant, int k)
 {
     if (variant == 2) return 8;
     return variant == 0 || k > 4 ? 16 : 32;
 }
 
-int count_tpi(int variant, int k)
-{
-    if (variant < 3) return 1;
-    if (k <= 1) return 4;
-    if (k == 2 || (k == 3 && variant == 4)) return 2;
-    return 1;
-}
-
 CountFn count_fn(int k, int variant, bool udf)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (count_tpi(variant, k)) {
-    case 4:
-        if (k == 0) return udf ? count_kernel<0, 32, true, 4> : count_kernel<0, 32, false, 4>;
-        return udf ? count_kernel<1, 32, true, 4> : count_kernel<1, 32, false, 4>;
-    case 2:
-        if (k == 2) return udf ? count_kernel<2, 32, true, 2> : count_kernel<2, 32, false, 2>;
-        return udf ? count_kernel<3, 32, true, 2> : count_kernel<3, 32, false, 2>;
-    default: break;
-    }
     switch (count_rpt(variant, k)) {
     case 8: return udf ? count_table_impl<8, true>(k, S{}) : count_table_impl<8, false>(k, S{});
     case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
