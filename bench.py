@@ -578,7 +578,10 @@ def planning_workload(args):
         "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s",
         "plain": strip(plain), "batched": strip(batched), "batched_gate": strip(gated),
         "batched_gate_exact_probe": strip(gated_p),
-        "gate_speedup_vs_plain": round(gated["predicates_per_s"] / plain["predicates_per_s"], 2),
+        "capacity_gate_speedup_vs_plain": round(sat_gated["predicates_per_s"] / sat_plain["predicates_per_s"], 2),
+        "offered_load_gate_speedup_vs_plain": round(gated["predicates_per_s"] / plain["predicates_per_s"], 2),
+        "offered_load_note": "at 2000 queries/s the 3000 selections arrive over 0.5 s, so no mode exceeds "
+                             "6000 predicates/s; capacity = the same queries offered at 100,000/s",
         "saturated_100k_per_s": {"plain": strip(sat_plain), "batched": strip(sat_batched), "batched_gate": strip(sat_gated),
                                  "gate_speedup_vs_plain": round(sat_gated["predicates_per_s"] /
                                                                 sat_plain["predicates_per_s"], 2),
