@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--planning", action="store_true", help="planning workload (1,000 three-table queries)")
     ap.add_argument("--copy-ref", action="store_true", help="1 GiB device copy (counter calibration)")
     ap.add_argument("--batched", action="store_true", help="batched workload only (256 sub-queries, 8 tables)")
+    ap.add_argument("--policy", action="store_true", help="materialization policy: calibrated cost model vs measured costs")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
@@ -169,6 +170,8 @@ def main():
         return learned_workload(args)
     if args.planning:
         return planning_workload(args)
+    if args.policy:
+        return policy_workload()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only (sharding by rows across GPUs is designed, "
                                    "not implemented): --gpus must be 1"}))
@@ -377,6 +380,19 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
             "batched_opts": b.opts(), "autotune_s": round(tune_s, 2)}
 
 
+def cpu_baseline_plain(t, want):
+    """cpu_baseline leg of the plain-latency extra: the oracle's count of the
+    Section 1 selection on the same 1M-row table, one host thread."""
+    from oracle import scan
+    from paper_1901_01488_amd import datagen as dg
+    a = time.perf_counter()
+    got = scan.count(t, dg.pred_plain(t, 0))
+    oracle_s = time.perf_counter() - a
+    assert got == want
+    return {"value": round(oracle_s / t.nrows * 1e9, 2), "unit": "ns/row", "cores": 1, "kind": "oracle",
+            "sample": "count(*) of the Section 1 selection over all 1M rows"}
+
+
 def plain_latency(ctx, esc, dg, torch, dev, reps=1000):
     """The Section 1 selection on a 1M-row table: wall latency of esc_count
     and esc_materialize (launch to result on the host), p50/p99."""
@@ -399,12 +415,7 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=1000):
         c = time.perf_counter()
         tc.append((b - a) * 1e6)
         tm.append((c - b) * 1e6)
-    from oracle import scan
-    a = time.perf_counter()
-    want = scan.count(t, dg.pred_plain(t, 0))
-    oracle_s = time.perf_counter() - a
-    assert want == n
-    return {"plain_1M_oracle_ns_per_row": round(oracle_s / t.nrows * 1e9, 2),
+    return {"plain_1M_cpu_baseline": cpu_baseline_plain(t, n),
             "plain_1M_count_us_p50": round(float(np.percentile(tc, 50)), 1),
             "plain_1M_count_us_p99": round(float(np.percentile(tc, 99)), 1),
             "plain_1M_materialize_us_p50": round(float(np.percentile(tm, 50)), 1),
@@ -504,8 +515,10 @@ def learned_workload(args):
         "qerror_median": float(np.median(q)), "qerror_p90": float(np.quantile(q, 0.9)),
         "qerror_p99": float(np.quantile(q, 0.99)), "qerror_max": float(q.max()), "beta": beta,
         "routed_fraction": float(route.mean()), "routed_count_errors": int((exact != counts[idx]).sum()),
-        "oracle_checked": len(check), "oracle_checked_note": "1000 random labels + every routed test predicate",
-        "oracle_errors": oracle_errors, "oracle_processes": workers, "oracle_s": round(oracle_s, 1),
+        "cpu_baseline": {"value": round(len(check) * n / oracle_s, 1), "unit": "row-predicates/s",
+                         "cores": workers, "kind": "oracle",
+                         "sample": "1000 random labels + every routed test predicate, one process per core",
+                         "checked": len(check), "errors": oracle_errors, "seconds": round(oracle_s, 1)},
         "predicate_gen_s": round(gen_s, 1)}),
         flush=True)
 
@@ -565,13 +578,15 @@ def planning_workload(args):
                                             planning.plans(est_sel, [t.nrows for t in tabs], gcfg))])
     # the oracle checks the exact counts: every selection on R and S, a
     # seeded sample of 48 on the 1B-row P
-    oracle_errors, oracle_checked = 0, 0
+    oracle_errors, oracle_checked, oracle_rows, oracle_s = 0, 0, 0, 0.0
     for ti, tab in enumerate(tabs):
         idx = list(range(nq)) if ti < 2 else sorted(np.random.default_rng(5).choice(nq, 48, replace=False).tolist())
         log(f"planning: oracle on table {ti} ({len(idx)} selections)")
-        got, workers, _ = oracle_counts(tab.host(), [q[ti] for q in queries], idx, f"planning table {ti}")
+        got, workers, sec = oracle_counts(tab.host(), [q[ti] for q in queries], idx, f"planning table {ti}")
         oracle_errors += sum(int(plain["counts"][i, ti]) != got[i] for i in idx)
         oracle_checked += len(idx)
+        oracle_rows += len(idx) * tab.nrows
+        oracle_s += sec
     strip = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()
                        if k not in ("counts", "est", "routed")}
     print(json.dumps({
@@ -591,8 +606,91 @@ def planning_workload(args):
         "routed_count_errors": int((gated["counts"][r] != plain["counts"][r]).sum()),
         "batched_count_errors": int((batched["counts"] != plain["counts"]).sum()),
         "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1),
-        "oracle_checked": oracle_checked, "oracle_errors": oracle_errors,
-        "oracle_note": "every selection on the 10M and 100M tables, 48 seeded ones on the 1B table"}), flush=True)
+        "cpu_baseline": {"value": round(oracle_rows / oracle_s, 1), "unit": "row-predicates/s", "cores": workers,
+                         "kind": "oracle", "sample": "every selection on the 10M and 100M tables, 48 seeded ones "
+                                                     "on the 1B table, one process per core",
+                         "checked": oracle_checked, "errors": oracle_errors, "seconds": round(oracle_s, 1)}}),
+        flush=True)
+
+
+def policy_workload():
+    """Materialization policy on the 100M-row planning table: the cost model
+    is calibrated with the library's kernels, then its keep / discard
+    decisions for `lt k` selections over five decades of selectivity are
+    compared with the measured cheaper option, next to a fixed threshold
+    tau = 0.05 and the two trivial policies."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc, policy
+    torch.cuda.init()
+    ctx = esc.Context(0)
+    t = dg.tables_planning([100_000_000], device="cuda:0")[0]
+    dt = esc.Table(t.nrows, t.dtypes, t.cols)
+    n = t.nrows
+    proj, scan_cols = [1, 2], 3          # selection on column 0, columns 1 and 2 projected
+    log("policy: calibration")
+    model, det = policy.calibrate(ctx, dt, 0, proj, scan_cols)
+    md = policy.model_dict(model)
+    # measured costs per selection: re-reading the table (scan_cols columns)
+    # vs the write pass plus reading the temporary table
+    scratch = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    evict = lambda: scratch.sum()
+    p_all = esc.Pred(dt, policy._touch_all(scan_cols))
+    ws_c = ctx.workspace(dt, False, key="pol-scan")
+    dcnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    scan_ms = policy._time_ms(torch, lambda: ctx.count_async(dt, p_all, dcnt, ws_c), 5, evict)
+    fracs = np.logspace(-5, np.log10(0.8), 24)
+    ks = [int(f * n) for f in fracs]
+    ws_m = ctx.workspace(dt, True, key="pol-mat")
+    cap = max(ks)
+    rowids = torch.empty(cap, dtype=torch.int32, device="cuda:0")
+    outs = [torch.empty(cap, dtype=torch.int32, device="cuda:0") for _ in proj]
+    dmat = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    mat_ms, tmp_ms = [], []
+    for k in ks:
+        p = esc.Pred(dt, ("lt", 0, k))
+        w = []
+        for _ in range(3):
+            ctx.count(dt, p, ws=ws_m)
+            evict()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            ctx.materialize_async(dt, p, proj, rowids, outs, cap, dmat, ws_m)
+            b.record()
+            torch.cuda.synchronize()
+            w.append(a.elapsed_time(b))
+        assert int(dmat.item()) == k
+        mat_ms.append(float(np.median(w)))
+        tmp = esc.Table(k, [esc.INT32] * 3, [rowids[:k]] + [o[:k] for o in outs])
+        pt = esc.Pred(tmp, policy._touch_all(3))
+        ws_t = ctx.workspace(tmp, False, key=("pol-tmp", k))
+        tmp_ms.append(policy._time_ms(torch, lambda: ctx.count_async(tmp, pt, dcnt, ws_t), 3, evict))
+    out = {"workload": "materialization policy: 100M x 4 planning table, selection on the key, 2 projected columns",
+           "model": md, "calibration": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in det.items()
+                                        if k != "mat_ms"}, "by_reuses": {}}
+    for r in (1, 2, 4):
+        t_scan = np.full(len(ks), r * scan_ms)
+        t_mat = np.asarray(mat_ms) + r * np.asarray(tmp_ms)
+        best = t_mat < t_scan
+        keep, _ = esc.policy_keep(model, n, np.asarray(ks, np.uint64), scan_cols, len(proj), r)
+        tau, min_rows = esc.policy_thresholds(model, n, scan_cols, len(proj), r)
+        pols = {"model": keep, "fixed_tau_0.05": np.asarray(fracs) < 0.05, "always": np.ones(len(ks), bool),
+                "never": np.zeros(len(ks), bool)}
+        opt = np.where(best, t_mat, t_scan).sum()
+        res = {}
+        for name, dec in pols.items():
+            cost = np.where(dec, t_mat, t_scan).sum()
+            res[name] = {"agreement": round(float(np.mean(dec == best)), 3),
+                         "cost_ms": round(float(cost), 3), "regret_pct": round(100.0 * (cost / opt - 1.0), 2)}
+        cross = [float(f) for f, a, b in zip(fracs, best[:-1], best[1:]) if a != b]
+        out["by_reuses"][str(r)] = {"tau_model": round(tau, 5), "min_rows_model": round(min_rows),
+                                    "measured_crossover_selectivity_above": cross[:1],
+                                    "optimal_cost_ms": round(float(opt), 3), "policies": res}
+    out["selectivities"] = [float(f) for f in fracs]
+    out["measured_ms"] = {"scan": round(scan_ms, 4), "write": [round(v, 4) for v in mat_ms],
+                          "tmp_read": [round(v, 4) for v in tmp_ms]}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

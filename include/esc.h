@@ -133,6 +133,10 @@ int esc_ctx_create(int device, esc_ctx **out);
 int esc_ctx_destroy(esc_ctx *ctx);
 /* Number of compute units of the context's device. */
 int esc_ctx_num_cus(const esc_ctx *ctx, int *out);
+/* Fraction of a wave tile's rows that must qualify for the materialization
+ * to read the tile's projected columns whole rather than gather them
+ * (1/128 unless ESC_DENSE_SHIFT sets another power of two). */
+int esc_ctx_dense_fraction(const esc_ctx *ctx, double *out);
 
 /* ------------------------------------------------------------------ tables
  *
@@ -334,6 +338,49 @@ int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau
  * within a factor beta^2 of each other, so their join order could flip. */
 int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta,
                        uint8_t *route);
+
+/* ------------------------------------------------------------------ materialization policy
+ *
+ * Section 2.1: materializing a pushed-down selection pays only when enough
+ * rows are pruned (the call overhead and the extra memory traffic must be
+ * won back) and only on tables large enough; the paper leaves the minimum
+ * table size and the maximum selectivity to the DBA and names adaptive
+ * choices as future work.  Here both follow from a cost model whose
+ * parameters are measured on the device.  For a selection of count rows
+ * out of nrows, s = count / nrows, p projected columns, k distinct columns
+ * read by a re-read of the table and r later uses:
+ *   without the temporary table, every use re-reads the table:
+ *     T_scan = r * nrows * 4k / scan_bytes_per_s
+ *   with it (the materialization gathers projected values while
+ *   s < dense_fraction and reads the projected columns whole above):
+ *     T_mat  = fixed_s + count * sparse_row_s          (count = 0 or s < dense_fraction)
+ *            = fixed_s + nrows * 4p / dense_bytes_per_s + count * dense_row_s   (otherwise)
+ *            + r * count * 4 (1 + p) / tmp_bytes_per_s     (reading row ids and values)
+ * Keep (materialize) when T_mat < T_scan.  Every expression is evaluated
+ * left to right in double precision. */
+typedef struct {
+    double scan_bytes_per_s;   /* streaming read rate of a selection scan */
+    double fixed_s;            /* materialization cost per call (launches, offsets) */
+    double sparse_row_s;       /* per qualifying row while projected values are gathered */
+    double dense_fraction;     /* selectivity from which projected columns are read whole */
+    double dense_bytes_per_s;  /* read rate of whole projected columns */
+    double dense_row_s;        /* per qualifying row when columns are read whole */
+    double tmp_bytes_per_s;    /* read rate of a temporary table */
+} esc_cost_model;
+
+/* keep[i] = 1 when materializing selection i is cheaper; saving_s[i] (may
+ * be NULL) = T_scan - T_mat.  scan_cols (k), proj_cols (p) and reuses (r)
+ * apply to all n selections.  Errors: ESC_ERR_INVALID (null pointers, n < 0,
+ * nrows[i] < 0, count[i] > nrows[i], a rate not positive, a cost negative,
+ * dense_fraction outside [0, 1], scan_cols < 1, proj_cols < 0, reuses < 1). */
+int esc_policy_keep(const esc_cost_model *m, const int64_t *nrows, const uint64_t *count, int n, int scan_cols,
+                    int proj_cols, int reuses, uint8_t *keep, double *saving_s);
+/* The two DBA parameters of Section 2.1 implied by the model for a table
+ * shape: *tau = the selectivity up to which materializing pays (keep holds
+ * for every s < tau, in [0, 1]) and *min_rows = the smallest table on which
+ * materializing even an empty result pays (T_scan > fixed_s). */
+int esc_policy_thresholds(const esc_cost_model *m, int64_t nrows, int scan_cols, int proj_cols, int reuses,
+                          double *tau, double *min_rows);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,7 @@ ARCH = "gfx950"
 SOURCES = [
     "esc_compile.cpp",
     "esc_features.cpp",
+    "esc_policy.cpp",
     "esc_api.hip",
     "esc_scan.hip",
     "esc_batch.hip",

@@ -2,6 +2,7 @@
 // esc_materialize: validation, choice of the kernel variant, launch and the
 // 8-byte (or 64-byte) read-back of the result.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -176,6 +177,13 @@ int esc_ctx_num_cus(const esc_ctx *ctx, int *out)
 {
     if (!ctx || !out) return fail(ESC_ERR_INVALID, "null argument");
     *out = ctx->num_cus;
+    return ESC_OK;
+}
+
+int esc_ctx_dense_fraction(const esc_ctx *ctx, double *out)
+{
+    if (!ctx || !out) return fail(ESC_ERR_INVALID, "null argument");
+    *out = ldexp(1.0, -ctx->dense_shift);
     return ESC_OK;
 }
 

@@ -63,6 +63,13 @@ class PredInfo(ctypes.Structure):
                 ("pad", ctypes.c_int32)]
 
 
+class CostModel(ctypes.Structure):
+    _fields_ = [("scan_bytes_per_s", ctypes.c_double), ("fixed_s", ctypes.c_double),
+                ("sparse_row_s", ctypes.c_double), ("dense_fraction", ctypes.c_double),
+                ("dense_bytes_per_s", ctypes.c_double), ("dense_row_s", ctypes.c_double),
+                ("tmp_bytes_per_s", ctypes.c_double)]
+
+
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
@@ -117,6 +124,10 @@ def lib():
             "esc_mlp_train": ([vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_float, vp, vp], ctypes.c_int),
             "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
             "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
+            "esc_ctx_dense_fraction": ([vp, vp], ctypes.c_int),
+            "esc_policy_keep": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
+                                ctypes.c_int),
+            "esc_policy_thresholds": ([vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             if not hasattr(L, name):
@@ -287,6 +298,12 @@ class Context:
         n = ctypes.c_int()
         check(lib().esc_ctx_num_cus(self.h, ctypes.byref(n)))
         return n.value
+
+    def dense_fraction(self):
+        """Tile density from which the materialization reads projected columns whole."""
+        v = ctypes.c_double()
+        check(lib().esc_ctx_dense_fraction(self.h, ctypes.byref(v)))
+        return v.value
 
     def workspace(self, table: Table, materialize=True, key=None):
         """A zero-filled device workspace big enough for `table` (cached)."""
@@ -527,3 +544,22 @@ def gate_join_pair(yr, nr, ys, ns, beta):
     r = ctypes.c_uint8()
     check(lib().esc_gate_join_pair(float(yr), int(nr), float(ys), int(ns), float(beta), ctypes.byref(r)))
     return bool(r.value)
+
+
+def policy_keep(model: CostModel, nrows, counts, scan_cols, proj_cols, reuses=1):
+    """Materialize-or-not for each selection; returns (keep, saving_s)."""
+    c = np.ascontiguousarray(counts, np.uint64)
+    n = np.ascontiguousarray(np.broadcast_to(np.asarray(nrows, np.int64), c.shape))
+    keep = np.zeros(len(c), np.uint8)
+    saving = np.zeros(len(c), np.float64)
+    check(lib().esc_policy_keep(ctypes.byref(model), n.ctypes.data, c.ctypes.data, len(c), int(scan_cols),
+                                int(proj_cols), int(reuses), keep.ctypes.data, saving.ctypes.data))
+    return keep.astype(bool), saving
+
+
+def policy_thresholds(model: CostModel, nrows, scan_cols, proj_cols, reuses=1):
+    """(tau, min_rows) implied by the model for a table shape."""
+    tau, mr = ctypes.c_double(), ctypes.c_double()
+    check(lib().esc_policy_thresholds(ctypes.byref(model), int(nrows), int(scan_cols), int(proj_cols), int(reuses),
+                                      ctypes.byref(tau), ctypes.byref(mr)))
+    return tau.value, mr.value

@@ -1,0 +1,72 @@
+"""Materialization policy on the GPU: the cost model calibrated with the
+library's own kernels, decisions equal to the oracle's for that model, and
+agreement with the measured cheaper option where the margin is wide.
+
+The fitted rates are measurements (parity unpinned); what is pinned is the
+decision rule (the library against the oracle) and the counts behind it."""
+import numpy as np
+import pytest
+
+from oracle import policy as po
+from paper_1901_01488_amd import datagen as dg
+from paper_1901_01488_amd import esc, policy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    torch.cuda.init()
+    return esc.Context(0)
+
+
+def test_calibrated_policy(ctx):
+    import torch
+    t = dg.tables_planning([20_000_000], device="cuda:0")[0]
+    dt = esc.Table(t.nrows, t.dtypes, t.cols)
+    n = t.nrows
+    model, det = policy.calibrate(ctx, dt, 0, [1, 2], 3, reps=3)
+    md = policy.model_dict(model)
+    print(md, det)
+    assert 5e10 < md["scan_bytes_per_s"] < 8.1e12
+    assert 1e9 < md["tmp_bytes_per_s"] < 8.1e12
+    assert md["sparse_row_s"] > 0.0 and md["fixed_s"] > 0.0 and md["dense_fraction"] == 1 / 128
+    # materialization time grows with the number of rows written
+    mats = [det["mat_ms"][k] for k in sorted(det["mat_ms"])]
+    assert mats[-1] > mats[0]
+    # library decisions and thresholds equal the oracle's for the fitted model
+    counts = np.unique(np.linspace(0, n, 97).astype(np.uint64))
+    for r in (1, 2, 4):
+        keep, saving = esc.policy_keep(model, n, counts, 3, 2, r)
+        for c, k, s in zip(counts, keep, saving):
+            assert (k, s) == po.keep(md, n, int(c), 3, 2, r)
+        assert esc.policy_thresholds(model, n, 3, 2, r) == po.thresholds(md, n, 3, 2, r)
+    # far from the threshold the model agrees with the measured costs: a
+    # selection of 0.01 % of the rows is worth keeping, one of 90 % is not
+    tau, _ = esc.policy_thresholds(model, n, 3, 2, 1)
+    assert 1e-4 < tau < 0.9
+    scratch = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dcnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    p_all = esc.Pred(dt, policy._touch_all(3))
+    ws_c = ctx.workspace(dt, False, key="tp-scan")
+    scan_ms = policy._time_ms(torch, lambda: ctx.count_async(dt, p_all, dcnt, ws_c), 3, lambda: scratch.sum())
+    assert int(dcnt.item()) == n
+    ws_m = ctx.workspace(dt, True, key="tp-mat")
+    for frac, want_keep in ((1e-4, True), (0.9, False)):
+        k = int(frac * n)
+        rowids = torch.empty(k, dtype=torch.int32, device="cuda:0")
+        outs = [torch.empty(k, dtype=torch.int32, device="cuda:0") for _ in range(2)]
+        p = esc.Pred(dt, ("lt", 0, k))
+        assert ctx.count(dt, p, ws=ws_m) == k
+        dmat = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+        mat_ms = policy._time_ms(torch, lambda: ctx.materialize_async(dt, p, [1, 2], rowids, outs, k, dmat, ws_m), 3)
+        assert int(dmat.item()) == k
+        assert np.array_equal(rowids.cpu().numpy(), np.flatnonzero(t.cols[0].cpu().numpy() < k).astype(np.int32))
+        tmp = esc.Table(k, [esc.INT32] * 3, [rowids] + outs)
+        pt = esc.Pred(tmp, policy._touch_all(3))
+        ws_t = ctx.workspace(tmp, False, key=("tp-tmp", k))
+        tmp_ms = policy._time_ms(torch, lambda: ctx.count_async(tmp, pt, dcnt, ws_t), 3, lambda: scratch.sum())
+        measured_keep = mat_ms + tmp_ms < scan_ms
+        model_keep = bool(esc.policy_keep(model, n, [k], 3, 2, 1)[0][0])
+        assert measured_keep == model_keep == want_keep, (frac, mat_ms, tmp_ms, scan_ms)
