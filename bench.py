@@ -159,6 +159,7 @@ def main():
     ap.add_argument("--copy-ref", action="store_true", help="1 GiB device copy (counter calibration)")
     ap.add_argument("--batched", action="store_true", help="batched workload only (256 sub-queries, 8 tables)")
     ap.add_argument("--policy", action="store_true", help="materialization policy: calibrated cost model vs measured costs")
+    ap.add_argument("--join", action="store_true", help="star join over ESC temporary tables (10M / 100M build, 1B probe)")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
@@ -172,6 +173,8 @@ def main():
         return planning_workload(args)
     if args.policy:
         return policy_workload()
+    if args.join:
+        return join_workload()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only (sharding by rows across GPUs is designed, "
                                    "not implemented): --gpus must be 1"}))
@@ -691,6 +694,100 @@ def policy_workload():
     out["measured_ms"] = {"scan": round(scan_ms, 4), "write": [round(v, 4) for v in mat_ms],
                           "tmp_read": [round(v, 4) for v in tmp_ms]}
     print(json.dumps(out), flush=True)
+
+
+def join_workload():
+    """Star join P |x| sigma(R) |x| sigma(S) after exact selectivity
+    computation: the selections' exact counts order the probe's lookups (the
+    more selective build side first, so most probe rows stop after one
+    lookup), the selections are materialized (row id and key), hash tables
+    are built on the temporary tables and the 1B-row probe relation is
+    counted against both in one pass.  The reversed lookup order is timed
+    beside it."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc
+    torch.cuda.init()
+    dev = "cuda:0"
+    ctx = esc.Context(0)
+    log("join: tables")
+    R, S, P = dg.tables_join(device=dev)
+    dR, dS = esc.Table(R.nrows, R.dtypes, R.cols), esc.Table(S.nrows, S.dtypes, S.cols)
+    dP = esc.Table(P.nrows, P.dtypes, P.cols)
+    queries = [(("lt", 1, 5), ("eq", 1, 0)), (("between", 1, 10, 60), ("in", 1, [1, 2, 3, 5, 8])),
+               (("eq", 1, 42), ("lt", 1, 1000)), (("lt", 1, 50), ("gt", 1, 20))]
+    scratch = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+
+    def timed(fn, reps=3):
+        out = []
+        for _ in range(reps):
+            scratch.sum()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            r = fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return r, float(np.median(out))
+
+    res = []
+    sample = 20_000_000
+    P_pre = esc.Table(sample, P.dtypes, [c[:sample] for c in P.cols])
+    for qr, qs in queries:
+        log(f"join: {qr} {qs}")
+        t0 = time.perf_counter()
+        sides = []
+        for name, dt, q in (("R", dR, qr), ("S", dS, qs)):
+            p = esc.Pred(dt, q)
+            c = ctx.count(dt, p)
+            ids = torch.empty(max(c, 1), dtype=torch.int32, device=dev)
+            key = torch.empty(max(c, 1), dtype=torch.int32, device=dev)
+            assert ctx.materialize(dt, p, [0], ids, [key], c) == c
+            sides.append({"name": name, "count": c, "sel": c / dt.nrows, "key": key[:c]})
+        tabs = []
+        build_ms = 0.0
+        for sd in sides:
+            tab, ms = timed(lambda: ctx.hash_table(sd["key"]), 3)
+            build_ms += ms
+            tabs.append(tab)
+        order = sorted(range(2), key=lambda j: sides[j]["sel"])     # the more selective side first
+        cols = [0, 1]
+        got, probe_ms = timed(lambda: ctx.join_count(dP, [cols[j] for j in order], [tabs[j] for j in order]))
+        got_rev, probe_rev_ms = timed(lambda: ctx.join_count(dP, [cols[j] for j in order[::-1]],
+                                                             [tabs[j] for j in order[::-1]]))
+        assert got == got_rev
+        pipeline_s = time.perf_counter() - t0
+        pre = ctx.join_count(P_pre, [0, 1], tabs)
+        res.append({"sel_R": round(sides[0]["sel"], 5), "sel_S": round(sides[1]["sel"], 5),
+                    "build_rows": [sd["count"] for sd in sides], "join_rows": got,
+                    "build_ms": round(build_ms, 3), "probe_ms": round(probe_ms, 3),
+                    "probe_reversed_ms": round(probe_rev_ms, 3),
+                    "order_speedup": round(probe_rev_ms / probe_ms, 2),
+                    "probe_rows_per_s": round(P.nrows / (probe_ms * 1e-3), 1),
+                    "probe_stream_GBps": round(P.nrows * 8 / (probe_ms * 1e-3) / 1e9, 1),
+                    "pipeline_s": round(pipeline_s, 3), "prefix_rows": sample, "prefix_join_rows": pre,
+                    "_keys": [sd["key"] for sd in sides]})
+    # cpu_baseline: the oracle's join count over the first 20M probe rows
+    from oracle import join as oj
+    p_host = [c[:sample].cpu().numpy() for c in P.cols]
+    errors, osec = 0, 0.0
+    for r in res:
+        keys = [k.cpu().numpy() for k in r.pop("_keys")]
+        a = time.perf_counter()
+        want = oj.count(p_host, keys)
+        osec += time.perf_counter() - a
+        errors += int(want != r["prefix_join_rows"])
+    best = max(res, key=lambda r: r["probe_stream_GBps"])
+    print(json.dumps({
+        "workload": "star join: P (1B rows, 2 foreign keys) with sigma(R) (10M) and sigma(S) (100M)",
+        "queries": res,
+        "roofline_probe": {"bound": "hbm", "achieved": best["probe_stream_GBps"], "peak": 8000.0, "unit": "GB/s",
+                           "frac": round(best["probe_stream_GBps"] / 8000.0, 4),
+                           "note": "8 bytes per probe row streamed; hash lookups are extra random reads"},
+        "cpu_baseline": {"value": round(len(res) * sample / osec, 1), "unit": "probe rows/s", "cores": 1,
+                         "kind": "oracle", "sample": f"join count over the first {sample} probe rows, each query",
+                         "errors": errors}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 4
+#define ESC_ABI_VERSION 5
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -338,6 +338,30 @@ int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau
  * within a factor beta^2 of each other, so their join order could flip. */
 int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta,
                        uint8_t *route);
+
+/* ------------------------------------------------------------------ hash join
+ *
+ * Section 2.2: a left-deep plan probes the largest relation and builds hash
+ * tables on the others, whose pushed-down selections (Section 2.1) leave
+ * them as temporary tables.  A hash table lives in caller-owned device
+ * memory of esc_hash_table_bytes(nkeys) bytes: open addressing with linear
+ * probing over a power of two of 8-byte slots, at least two per key and at
+ * least 64; several rows may share a key.  The table keeps each key with
+ * the index of its build row. */
+int esc_hash_table_bytes(int64_t nkeys, size_t *bytes);
+/* Clears the table and inserts dev_keys[0 .. nkeys) (device int32), enqueued
+ * on `stream`.  Errors: ESC_ERR_INVALID (null pointers, nkeys < 0, a size not
+ * from esc_hash_table_bytes, fewer than 2 * nkeys slots), ESC_ERR_UNSUPPORTED
+ * (more than 2^30 keys). */
+int esc_hash_build(esc_ctx *ctx, const int32_t *dev_keys, int64_t nkeys, void *dev_table, size_t table_bytes,
+                   void *stream);
+/* Rows of the star join of `probe` with ntables (1..4) build sides: the sum
+ * over probe rows i of the product over j of the number of build rows of
+ * table j whose key equals probe column key_cols[j] at row i (int32 or
+ * date32 columns).  Waits for the result.  The product of one row must fit
+ * in 64 bits.  Errors: ESC_ERR_INVALID, ESC_ERR_TYPE (a float32 key column). */
+int esc_join_count(esc_ctx *ctx, const esc_table *probe, const int32_t *key_cols, void *const *dev_tables,
+                   const size_t *table_bytes, int ntables, void *stream, uint64_t *out_count);
 
 /* ------------------------------------------------------------------ materialization policy
  *

@@ -26,6 +26,7 @@ SOURCES = [
     "esc_api.hip",
     "esc_scan.hip",
     "esc_batch.hip",
+    "esc_join.hip",
     "esc_mlp.hip",
 ]
 

@@ -169,6 +169,7 @@ int esc_ctx_destroy(esc_ctx *ctx)
     forget_tiles(ctx, nullptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->conj_dev) (void)hipFree(ctx->conj_dev);
+    if (ctx->join_dev) (void)hipFree(ctx->join_dev);
     delete ctx;
     return ESC_OK;
 }

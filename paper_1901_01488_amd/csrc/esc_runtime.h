@@ -15,6 +15,7 @@ struct esc_ctx {
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)
     int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
     void *conj_dev = nullptr;               // split selectivities: programs + counters (allocated on first use)
+    void *join_dev = nullptr;               // join count (allocated on first use)
 };
 
 namespace esc {

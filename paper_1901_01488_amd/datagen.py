@@ -280,6 +280,25 @@ def tables_planning(sizes=None, device=None):
             for t, n in enumerate(sizes)]
 
 
+JOIN_SIZES = (10_000_000, 100_000_000, 1_000_000_000)
+
+
+def tables_join(sizes=JOIN_SIZES, device=None):
+    """Star schema of the join workload: build relations R and S (a key that
+    is a permutation of 0..n-1 and an attribute: U[0,100) for R, bounded
+    Zipf(1.1) over [0,10^5) for S) and the probe relation P with one foreign
+    key into each, uniform over the referenced keys."""
+    nr, ns, np_ = sizes
+    br, bs, bp = _backend(data_seed(6, 0), device), _backend(data_seed(6, 1), device), _backend(data_seed(6, 2), device)
+    R = Table("R", nr, [INT32, INT32], [br.perm(nr), br.uniform(0, 100, nr)], ["perm", "uniform"],
+              [(0, nr - 1), (0, 99)])
+    S = Table("S", ns, [INT32, INT32], [bs.perm(ns), bs.zipf(1.1, 100_000, ns)], ["perm", "zipf"],
+              [(0, ns - 1), (0, 99_999)])
+    P = Table("P", np_, [INT32, INT32], [bp.uniform(0, nr, np_), bp.uniform(0, ns, np_)], ["fk", "fk"],
+              [(0, nr - 1), (0, ns - 1)])
+    return R, S, P
+
+
 # ---------------------------------------------------------------- special tables for pins
 
 def table_edge_floats() -> Table:

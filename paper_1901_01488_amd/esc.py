@@ -75,7 +75,7 @@ class BatchOpts(ctypes.Structure):
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-ABI_VERSION = 4   # esc.h's ESC_ABI_VERSION for the struct layouts below
+ABI_VERSION = 5   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -125,6 +125,9 @@ def lib():
             "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
             "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
             "esc_ctx_dense_fraction": ([vp, vp], ctypes.c_int),
+            "esc_hash_table_bytes": ([i64, vp], ctypes.c_int),
+            "esc_hash_build": ([vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
+            "esc_join_count": ([vp, vp, vp, vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
             "esc_policy_keep": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
                                 ctypes.c_int),
             "esc_policy_thresholds": ([vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
@@ -298,6 +301,27 @@ class Context:
         n = ctypes.c_int()
         check(lib().esc_ctx_num_cus(self.h, ctypes.byref(n)))
         return n.value
+
+    def hash_table(self, keys, stream=None):
+        """Device hash table (a uint8 tensor) of an int32 device key tensor."""
+        import torch
+        nb = ctypes.c_size_t()
+        check(lib().esc_hash_table_bytes(int(keys.numel()), ctypes.byref(nb)))
+        tab = torch.empty(nb.value, dtype=torch.uint8, device=keys.device)
+        check(lib().esc_hash_build(self.h, ctypes.c_void_p(keys.data_ptr()) if keys.numel() else None,
+                                   int(keys.numel()), ctypes.c_void_p(tab.data_ptr()), nb.value,
+                                   _stream_handle(stream)))
+        return tab
+
+    def join_count(self, probe: Table, key_cols, tables, stream=None) -> int:
+        """Rows of the star join of `probe` (key_cols[j] against tables[j])."""
+        kc = np.asarray(key_cols, np.int32)
+        ptrs = (ctypes.c_void_p * len(tables))(*[t.data_ptr() for t in tables])
+        sizes = (ctypes.c_size_t * len(tables))(*[t.numel() for t in tables])
+        out = ctypes.c_uint64()
+        check(lib().esc_join_count(self.h, probe.h, kc.ctypes.data, ptrs, sizes, len(tables),
+                                   _stream_handle(stream), ctypes.byref(out)))
+        return out.value
 
     def dense_fraction(self):
         """Tile density from which the materialization reads projected columns whole."""
