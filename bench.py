@@ -160,6 +160,7 @@ def main():
     ap.add_argument("--batched", action="store_true", help="batched workload only (256 sub-queries, 8 tables)")
     ap.add_argument("--policy", action="store_true", help="materialization policy: calibrated cost model vs measured costs")
     ap.add_argument("--join", action="store_true", help="star join over ESC temporary tables (10M / 100M build, 1B probe)")
+    ap.add_argument("--typed", action="store_true", help="TEXT / DECIMAL(15,2) predicates (60M rows, 64 predicates)")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
@@ -175,6 +176,8 @@ def main():
         return policy_workload()
     if args.join:
         return join_workload()
+    if args.typed:
+        return typed_workload()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only (sharding by rows across GPUs is designed, "
                                    "not implemented): --gpus must be 1"}))
@@ -787,6 +790,74 @@ def join_workload():
                            "note": "8 bytes per probe row streamed; hash lookups are extra random reads"},
         "cpu_baseline": {"value": round(len(res) * sample / osec, 1), "unit": "probe rows/s", "cores": 1,
                          "kind": "oracle", "sample": f"join count over the first {sample} probe rows, each query",
+                         "errors": errors}}), flush=True)
+
+
+def typed_workload(n=60_000_000, npreds=64, sample=200_000):
+    """Predicates on TEXT and DECIMAL(15,2) columns (Section 3, Table 3):
+    each typed predicate is lowered onto the stored int32 columns
+    (dictionary codes, hundredths), compiled and counted.  Reports the
+    host-side lowering + compile time per predicate, the count's rate over
+    the columns it touches, and the typed oracle (strings and exact
+    decimals) on a row sample as the CPU baseline, whose counts must equal
+    the library's on the same sample."""
+    from decimal import Decimal
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc, types
+    from oracle import typed
+    torch.cuda.init()
+    ctx = esc.Context(0)
+    log("typed: columns")
+    vocab, idx, price, disc, qty = dg.typed_columns(n, dg.data_seed(7))
+    d = types.Dict(vocab)
+    code_of = np.array([d.range(esc.EQ, w)[0] for w in vocab], dtype=np.int32)
+    cols = [torch.from_numpy(code_of[idx]).cuda(), torch.from_numpy(price).cuda(),
+            torch.from_numpy(disc).cuda(), torch.from_numpy(qty).cuda()]
+    dt = esc.Table(n, [dg.INT32] * 4, cols)
+    dt_pre = esc.Table(sample, [dg.INT32] * 4, [c[:sample] for c in cols])
+    tmap = {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2)}
+    preds = dg.typed_preds(vocab, np.random.default_rng(dg.pred_seed(7)), npreds)
+    a = time.perf_counter()
+    cps = [esc.Pred(dt, types.lower(p, tmap)) for p in preds]
+    lower_ms = (time.perf_counter() - a) * 1e3 / npreds
+    for cp in cps[:4]:
+        ctx.count(dt, cp)
+    torch.cuda.synchronize()
+    ms, gbps, counts = [], [], []
+    for p, cp in zip(preds, cps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        c = ctx.count(dt, cp)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1])
+        ms.append(t)
+        gbps.append(4 * n * len(pred_columns(p)) / (t * 1e-3) / 1e9)
+        counts.append(c)
+    log("typed: oracle sample")
+    text = np.array(vocab, dtype=object)[idx[:sample]]
+    raw = [list(text), [Decimal(int(c)).scaleb(-2) for c in price[:sample]],
+           [Decimal(int(c)).scaleb(-2) for c in disc[:sample]], qty[:sample]]
+    kinds = ["text", "decimal", "decimal", "int"]
+    errors, osec, nq = 0, 0.0, 0
+    for p, cp in zip(preds, cps):
+        a = time.perf_counter()
+        want = typed.count(raw, kinds, p)
+        osec += time.perf_counter() - a
+        nq += 1
+        errors += int(want != ctx.count(dt_pre, cp))
+        if osec > 20:
+            break
+    print(json.dumps({
+        "workload": f"TEXT (2,000-word dictionary, Zipf 1.05) / DECIMAL(15,2) x2 / INTEGER, {n} rows, "
+                    f"{npreds} typed predicates",
+        "lower_compile_ms_per_predicate": round(lower_ms, 3),
+        "count_ms_p50": round(float(np.median(ms)), 4), "count_ms_max": round(float(np.max(ms)), 4),
+        "count_GBps_p50": round(float(np.median(gbps)), 1),
+        "selectivity_p50": round(float(np.median(counts)) / n, 5),
+        "cpu_baseline": {"value": round(nq * sample / osec, 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
+                         "sample": f"typed oracle on the first {sample} rows, {nq} predicates",
                          "errors": errors}}), flush=True)
 
 

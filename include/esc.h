@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 5
+#define ESC_ABI_VERSION 6
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -338,6 +338,43 @@ int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau
  * within a factor beta^2 of each other, so their join order could flip. */
 int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta,
                        uint8_t *route);
+
+/* ------------------------------------------------------------------ TEXT and DECIMAL columns
+ *
+ * Section 3 (Table 3) evaluates predicates on TEXT and DECIMAL(15,2)
+ * columns beside INTEGER ones.  Both are stored as 4-byte columns, so the
+ * scans keep their coalesced loads and exact int32 tests, and their
+ * predicates are written on the stored values (dtype ESC_INT32):
+ *  - TEXT is dictionary-coded: a column holds each value's code, its rank
+ *    in the dictionary's byte-wise order, so string comparisons are code
+ *    comparisons and a prefix is a code interval;
+ *  - DECIMAL(p, s) holds value * 10^s as int32 (|value| * 10^s < 2^31), and
+ *    a decimal literal becomes an exact int32 bound. */
+typedef struct esc_dict esc_dict;
+enum { ESC_DICT_PREFIX = 100 };   /* esc_dict_range: strings starting with s */
+
+/* A dictionary of n distinct strings (any order; the dictionary sorts them
+ * byte-wise).  Errors: ESC_ERR_INVALID (null pointers, duplicates). */
+int esc_dict_create(const char *const *strings, int n, esc_dict **out);
+int esc_dict_destroy(esc_dict *d);
+int esc_dict_size(const esc_dict *d, int *n);
+/* *code = rank of s, or -1 when s is not in the dictionary. */
+int esc_dict_code(const esc_dict *d, const char *s, int32_t *code);
+/* The string of a code (owned by the dictionary). */
+int esc_dict_string(const esc_dict *d, int32_t code, const char **s);
+/* Codes [*lo, *hi] of the strings x with: x = s (ESC_EQ), x < s (ESC_LT),
+ * x > s (ESC_GT), s <= x <= s2 (ESC_BETWEEN), x starts with s
+ * (ESC_DICT_PREFIX); byte-wise comparison.  None: *lo = 0, *hi = -1. */
+int esc_dict_range(const esc_dict *d, int op, const char *s, const char *s2, int32_t *lo, int32_t *hi);
+/* For a decimal literal c ([+-]digits[.digits]) and scale s: ESC_EQ: the
+ * stored value equal to c (*empty = 1 when c has more than s nonzero
+ * decimals, so nothing equals it); ESC_LT: the largest stored value below c;
+ * ESC_GT: the smallest stored value above c.  Exact, no floating point.
+ * A literal of 10^18 or more in stored units (literal * 10^s) saturates to
+ * +-(10^18 + 1/2), which gives the same bounds for every stored value below
+ * 10^18 in magnitude (all int32 values).
+ * Errors: ESC_ERR_INVALID (bad literal, scale outside [0, 9]). */
+int esc_decimal_bound(const char *literal, int scale, int op, int64_t *bound, int *empty);
 
 /* ------------------------------------------------------------------ hash join
  *

@@ -23,6 +23,7 @@ SOURCES = [
     "esc_compile.cpp",
     "esc_features.cpp",
     "esc_policy.cpp",
+    "esc_types.cpp",
     "esc_api.hip",
     "esc_scan.hip",
     "esc_batch.hip",

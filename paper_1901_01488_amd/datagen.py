@@ -299,6 +299,106 @@ def tables_join(sizes=JOIN_SIZES, device=None):
     return R, S, P
 
 
+# ---------------------------------------------------------------- TEXT and DECIMAL columns
+
+def typed_vocab(k, seed):
+    """k distinct strings: lowercase words of 1..12 letters drawn from a
+    few shared stems (so that prefixes group many of them), a few with
+    non-ASCII letters, and the empty string."""
+    rng = np.random.default_rng(seed)
+    stems = ["", "al", "bra", "ca", "car", "dark", "gold", "ivo", "lin", "ma", "mi", "ro", "sa", "sm"]
+    extra = ["é", "ü", "ß", "中", "~"]
+    letters = np.array(list("abcdefghijklmnopqrstuvwxyz"))
+    out = {""}
+    while len(out) < k:
+        w = stems[rng.integers(len(stems))] + "".join(rng.choice(letters, rng.integers(0, 9)))
+        if rng.random() < 0.03:
+            w += extra[rng.integers(len(extra))]
+        out.add(w[:12])
+    return sorted(out, key=lambda x: rng.random())   # no particular order
+
+
+def typed_columns(n, seed):
+    """Columns of the TEXT / DECIMAL workload (Section 3, Table 3): a TEXT
+    column given as indices into `vocab` (bounded Zipf(1.05) over 2,000
+    strings), a DECIMAL(15,2) price as hundredths in [90,000, 10,500,000)
+    (900.00 .. 104,999.99), a DECIMAL(15,2) discount in hundredths 0..10
+    (0.00 .. 0.10) and an INTEGER quantity 1..50."""
+    rng = np.random.default_rng(seed)
+    vocab = typed_vocab(2000, seed + 1)
+    cdf = _zipf_cdf(1.05, len(vocab))
+    idx = np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), len(vocab) - 1).astype(np.int32)
+    price = rng.integers(90_000, 10_500_000, n).astype(np.int32)
+    disc = rng.integers(0, 11, n).astype(np.int32)
+    qty = rng.integers(1, 51, n).astype(np.int32)
+    return vocab, idx, price, disc, qty
+
+
+def _dec_literal(rng, lo, hi):
+    """A decimal literal between lo and hi (in units) with 0..4 decimals."""
+    d = int(rng.integers(0, 5))
+    v = rng.uniform(lo, hi)
+    return ("%.*f" % (d, v)) if d else str(int(round(v)))
+
+
+def typed_preds(vocab, rng, count):
+    """Predicates over (text, price, discount, quantity) = columns 0..3 in
+    the typed leaf forms: strings on column 0 (present ones, absent ones,
+    prefixes), decimal literals on columns 1 and 2 (some with more decimals
+    than the scale, some outside the stored range) and ints on column 3."""
+    def s_any():
+        r = rng.random()
+        w = vocab[rng.integers(len(vocab))]
+        if r < 0.6:
+            return w
+        if r < 0.8:
+            return w + "m"             # most likely absent
+        return w[: int(rng.integers(0, len(w) + 1))]
+
+    def leaf():
+        c = int(rng.integers(0, 4))
+        if c == 0:
+            op = ["eq", "lt", "gt", "between", "in", "prefix"][rng.integers(6)]
+            if op == "between":
+                a, b = sorted([s_any(), s_any()])
+                return ("between", 0, a, b) if rng.random() < 0.9 else ("between", 0, b, a)
+            if op == "in":
+                return ("in", 0, [s_any() for _ in range(int(rng.integers(1, 6)))])
+            if op == "prefix":
+                w = vocab[rng.integers(len(vocab))]
+                return ("prefix", 0, w[: int(rng.integers(0, 4))])
+            return (op, 0, s_any())
+        if c in (1, 2):
+            lo, hi = (900.0, 105_000.0) if c == 1 else (-0.02, 0.12)
+            if rng.random() < 0.05:
+                lo, hi = (-1e12, 1e12)     # far outside int32 hundredths
+            op = ["eq", "lt", "gt", "between", "in"][rng.integers(5)]
+            if op == "between":
+                a, b = _dec_literal(rng, lo, hi), _dec_literal(rng, lo, hi)
+                return ("between", c, a, b)
+            if op == "in":
+                return ("in", c, [_dec_literal(rng, lo, hi) for _ in range(int(rng.integers(1, 5)))])
+            if op == "eq" and c == 2:
+                return ("eq", 2, "0.0%d" % rng.integers(0, 10))
+            return (op, c, _dec_literal(rng, lo, hi))
+        op = ["eq", "lt", "gt", "between"][rng.integers(4)]
+        if op == "between":
+            a = int(rng.integers(0, 52))
+            return ("between", 3, a, a + int(rng.integers(0, 20)))
+        return (op, 3, int(rng.integers(0, 52)))
+
+    out = []
+    for _ in range(count):
+        k = int(rng.integers(1, 4))
+        if k == 1:
+            out.append(leaf())
+        elif rng.random() < 0.7:
+            out.append(("and", [leaf() for _ in range(k)]))
+        else:
+            out.append(("and", [leaf(), ("or", [leaf() for _ in range(k)])]))
+    return out
+
+
 # ---------------------------------------------------------------- special tables for pins
 
 def table_edge_floats() -> Table:

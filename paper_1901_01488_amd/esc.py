@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "TYPE", -3: "CAPACITY", -4: "ALIGN",
                 -7: "UNSUPPORTED", -8: "TIMEOUT"}
 
 AND, OR, EQ, LT, GT, BETWEEN, IN, UDF = range(8)
+DICT_PREFIX = 100
 _OPS = {"and": AND, "or": OR, "eq": EQ, "lt": LT, "gt": GT, "between": BETWEEN, "in": IN, "udf": UDF}
 U_LOAD, U_ADD, U_SUB, U_MUL, U_MOD, U_AND, U_OR, U_XOR, U_SHL, U_SHR = range(10)
 _UOPS = {"add": U_ADD, "sub": U_SUB, "mul": U_MUL, "mod": U_MOD, "band": U_AND, "bor": U_OR,
@@ -75,7 +76,7 @@ class BatchOpts(ctypes.Structure):
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-ABI_VERSION = 5   # esc.h's ESC_ABI_VERSION for the struct layouts below
+ABI_VERSION = 6   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -125,6 +126,13 @@ def lib():
             "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
             "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
             "esc_ctx_dense_fraction": ([vp, vp], ctypes.c_int),
+            "esc_dict_create": ([vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_dict_destroy": ([vp], ctypes.c_int),
+            "esc_dict_size": ([vp, vp], ctypes.c_int),
+            "esc_dict_code": ([vp, ctypes.c_char_p, vp], ctypes.c_int),
+            "esc_dict_string": ([vp, ctypes.c_int32, vp], ctypes.c_int),
+            "esc_dict_range": ([vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, vp, vp], ctypes.c_int),
+            "esc_decimal_bound": ([ctypes.c_char_p, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
             "esc_hash_table_bytes": ([i64, vp], ctypes.c_int),
             "esc_hash_build": ([vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "esc_join_count": ([vp, vp, vp, vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),

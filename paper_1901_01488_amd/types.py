@@ -1,0 +1,127 @@
+"""TEXT and DECIMAL predicate columns, lowered onto their 4-byte storage.
+
+Section 3 (Table 3) measures predicates on TEXT and DECIMAL(15,2) columns.
+Here a TEXT column is stored as dictionary codes (rank in the dictionary's
+byte-wise order) and a DECIMAL(p, s) column as value * 10^s in int32; the
+library translates a string or decimal comparison into a code range or an
+exact int32 bound (esc_dict_range, esc_decimal_bound), and `lower` rewrites
+a predicate description into int32 leaves on the stored values, which the
+ordinary compiler and kernels then evaluate.
+
+Extra leaf forms on typed columns: ("eq"|"lt"|"gt", c, v), ("between", c,
+a, b), ("in", c, [v...]) with str constants on TEXT columns and decimal
+literals (str or decimal.Decimal) on DECIMAL columns, and ("prefix", c, s)
+on TEXT columns.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import esc
+
+I32_MIN, I32_MAX = -2**31, 2**31 - 1
+
+
+def _c_str(s):
+    """UTF-8 bytes of s for a NUL-terminated C string (NUL is refused)."""
+    if "\x00" in s:
+        raise ValueError("TEXT values and literals may not contain NUL: %r" % s)
+    return s.encode()
+
+
+class Dict:
+    """An esc_dict over distinct strings (UTF-8; the byte-wise order is the
+    code-point order)."""
+
+    def __init__(self, strings):
+        strs = [_c_str(s) for s in strings]
+        arr = (ctypes.c_char_p * max(len(strs), 1))(*strs)
+        h = ctypes.c_void_p()
+        esc.check(esc.lib().esc_dict_create(arr, len(strs), ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int()
+        esc.check(esc.lib().esc_dict_size(self.h, ctypes.byref(n)))
+        out = ctypes.c_char_p()
+        self.strings = []
+        for c in range(n.value):
+            esc.check(esc.lib().esc_dict_string(self.h, c, ctypes.byref(out)))
+            self.strings.append(out.value.decode())
+
+    def encode(self, values):
+        """int32 codes of an array of strings (all in the dictionary)."""
+        sorted_arr = np.array(self.strings, dtype=object)
+        idx = {s: i for i, s in enumerate(sorted_arr)}
+        return np.fromiter((idx[v] for v in values), dtype=np.int32, count=len(values))
+
+    def range(self, op, s, s2=None):
+        lo, hi = ctypes.c_int32(), ctypes.c_int32()
+        esc.check(esc.lib().esc_dict_range(self.h, op, _c_str(s), _c_str(s2) if s2 is not None else None,
+                                           ctypes.byref(lo), ctypes.byref(hi)))
+        return lo.value, hi.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and esc._lib is not None:
+            esc._lib.esc_dict_destroy(self.h)
+            self.h = None
+
+
+def decimal_bound(literal, scale, op):
+    b, e = ctypes.c_int64(), ctypes.c_int()
+    esc.check(esc.lib().esc_decimal_bound(str(literal).encode(), int(scale), op, ctypes.byref(b), ctypes.byref(e)))
+    return b.value, bool(e.value)
+
+
+def _range_leaf(c, lo, hi):
+    """lo <= x <= hi on int32 column c (int64 bounds; empty -> false)."""
+    lo, hi = max(lo, I32_MIN), min(hi, I32_MAX)
+    if lo > hi:
+        return ("lt", c, I32_MIN)
+    return ("between", c, int(lo), int(hi))
+
+
+def _text_leaf(d: Dict, leaf):
+    op, c = leaf[0], leaf[1]
+    if op == "in":
+        codes = sorted({lo for lo, hi in (d.range(esc.EQ, v) for v in leaf[2]) if lo <= hi})
+        return ("in", c, codes) if codes else ("lt", c, I32_MIN)
+    if op == "prefix":
+        return _range_leaf(c, *d.range(esc.DICT_PREFIX, leaf[2]))
+    if op == "between":
+        return _range_leaf(c, *d.range(esc.BETWEEN, leaf[2], leaf[3]))
+    return _range_leaf(c, *d.range({"eq": esc.EQ, "lt": esc.LT, "gt": esc.GT}[op], leaf[2]))
+
+
+def _decimal_leaf(scale, leaf):
+    op, c = leaf[0], leaf[1]
+    if op == "in":
+        vals = sorted({v for v, e in (decimal_bound(x, scale, esc.EQ) for x in leaf[2]) if not e})
+        vals = [v for v in vals if I32_MIN <= v <= I32_MAX]
+        return ("in", c, vals) if vals else ("lt", c, I32_MIN)
+    if op == "eq":
+        v, empty = decimal_bound(leaf[2], scale, esc.EQ)
+        return ("lt", c, I32_MIN) if empty else _range_leaf(c, v, v)
+    if op == "lt":
+        return _range_leaf(c, I32_MIN, decimal_bound(leaf[2], scale, esc.LT)[0])
+    if op == "gt":
+        return _range_leaf(c, decimal_bound(leaf[2], scale, esc.GT)[0], I32_MAX)
+    if op == "between":   # a <= x <= b: above the largest value below a, below the smallest above b
+        lo = decimal_bound(leaf[2], scale, esc.LT)[0] + 1
+        hi = decimal_bound(leaf[3], scale, esc.GT)[0] - 1
+        return _range_leaf(c, lo, hi)
+    raise ValueError(f"{op} is not a decimal comparison")
+
+
+def lower(pred, types):
+    """Rewrites leaves on typed columns; types: {col: ("text", Dict) |
+    ("decimal", scale)}.  Other leaves are kept."""
+    op = pred[0]
+    if op in ("and", "or"):
+        return (op, [lower(q, types) for q in pred[1]])
+    if op == "udf" or pred[1] not in types:
+        return pred
+    kind, arg = types[pred[1]]
+    if kind == "text":
+        return _text_leaf(arg, pred)
+    return _decimal_leaf(arg, pred)
