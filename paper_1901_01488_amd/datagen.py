@@ -334,6 +334,36 @@ def typed_columns(n, seed):
     return vocab, idx, price, disc, qty
 
 
+WIDE_EDGES = [0, -1, 1, 2**31 - 1, 2**31, 2**32 - 1, 2**32, 2**32 + 1, -2**31, -2**31 - 1, -2**32,
+              -2**32 - 1, 10**15 - 1, -(10**15 - 1)]
+
+
+def typed_wide(n, seed):
+    """A DECIMAL(15,2) column beyond the int32 range, as int64 hundredths:
+    magnitude 10^U(0,15) (log-uniform over the whole precision), negative
+    with probability 0.2, and 1 % of the rows at the 32-bit word edges
+    (+-2^31, +-2^32, ...) and at +-(10^15 - 1)."""
+    rng = np.random.default_rng(seed)
+    mag = np.minimum(np.floor(10.0 ** rng.uniform(0, 15, n)), 10**15 - 1).astype(np.int64)
+    x = np.where(rng.random(n) < 0.2, -mag, mag)
+    edge = rng.random(n) < 0.01
+    x[edge] = np.array(WIDE_EDGES, dtype=np.int64)[rng.integers(0, len(WIDE_EDGES), int(edge.sum()))]
+    return x
+
+
+def _wide_literal(rng, present):
+    r = rng.random()
+    if r < 0.3 and len(present):
+        v = int(present[rng.integers(len(present))])          # a stored value, exactly
+        return ("-" if v < 0 else "") + "%d.%02d" % divmod(abs(v), 100)
+    if r < 0.45:
+        v = WIDE_EDGES[rng.integers(len(WIDE_EDGES))] + int(rng.integers(-1, 2))
+        return ("-" if v < 0 else "") + "%d.%02d" % divmod(abs(v), 100)
+    d = int(rng.integers(0, 5))
+    v = 10.0 ** rng.uniform(-2, 13.2) * (-1 if rng.random() < 0.3 else 1)
+    return ("%.*f" % (d, v)) if d else str(int(v))
+
+
 def _dec_literal(rng, lo, hi):
     """A decimal literal between lo and hi (in units) with 0..4 decimals."""
     d = int(rng.integers(0, 5))
@@ -341,11 +371,14 @@ def _dec_literal(rng, lo, hi):
     return ("%.*f" % (d, v)) if d else str(int(round(v)))
 
 
-def typed_preds(vocab, rng, count):
+def typed_preds(vocab, rng, count, wide=None):
     """Predicates over (text, price, discount, quantity) = columns 0..3 in
     the typed leaf forms: strings on column 0 (present ones, absent ones,
     prefixes), decimal literals on columns 1 and 2 (some with more decimals
-    than the scale, some outside the stored range) and ints on column 3."""
+    than the scale, some outside the stored range) and ints on column 3.
+    With `wide` (a sample of a typed_wide column's values), column 4 is
+    that DECIMAL(15,2) column, with literals from its values, its word
+    edges and log-uniform magnitudes."""
     def s_any():
         r = rng.random()
         w = vocab[rng.integers(len(vocab))]
@@ -356,7 +389,17 @@ def typed_preds(vocab, rng, count):
         return w[: int(rng.integers(0, len(w) + 1))]
 
     def leaf():
-        c = int(rng.integers(0, 4))
+        c = int(rng.integers(0, 5 if wide is not None else 4))
+        if c == 4:
+            op = ["eq", "lt", "gt", "between", "in"][rng.integers(5)]
+            if op == "between":
+                a, b = _wide_literal(rng, wide), _wide_literal(rng, wide)
+                if rng.random() < 0.8 and float(a) > float(b):
+                    a, b = b, a
+                return ("between", 4, a, b)
+            if op == "in":
+                return ("in", 4, [_wide_literal(rng, wide) for _ in range(int(rng.integers(1, 6)))])
+            return (op, 4, _wide_literal(rng, wide))
         if c == 0:
             op = ["eq", "lt", "gt", "between", "in", "prefix"][rng.integers(6)]
             if op == "between":

@@ -113,15 +113,102 @@ def _decimal_leaf(scale, leaf):
     raise ValueError(f"{op} is not a decimal comparison")
 
 
+# ---------------------------------------------------------------- 64-bit decimals as two word columns
+#
+# A DECIMAL(15,2) value needs up to 10^15 stored units, beyond int32.  Such
+# a column is stored as two 4-byte columns: H = the high 32 bits (signed)
+# and L = the low 32 bits with the sign bit flipped, so that the signed
+# order of L is the unsigned order of the low word.  The order of the 64-bit
+# values is then the lexicographic order of (H, L), and every comparison
+# with a 64-bit bound becomes a few int32 leaves on H and L; the scans keep
+# their 16-byte loads and 32-bit compares and read 8 bytes per row.
+
+def split_words(x):
+    """(H, L) int32 word columns of an int64 array (numpy or torch)."""
+    if isinstance(x, np.ndarray):
+        x = x.astype(np.int64)
+        hi = (x >> 32).astype(np.int32)
+        lo = ((x & 0xFFFFFFFF) ^ 0x80000000).astype(np.uint32).view(np.int32)
+        return hi, lo
+    import torch
+    hi = (x >> 32).to(torch.int32)
+    lo = ((x & 0xFFFFFFFF) ^ 0x80000000)
+    lo = torch.where(lo >= 2**31, lo - 2**32, lo).to(torch.int32)
+    return hi, lo
+
+
+def _words(c):
+    h = c >> 32
+    lo = (c & 0xFFFFFFFF) ^ 0x80000000
+    return h, lo - 2**32 if lo >= 2**31 else lo
+
+
+def _range64(H, L, lo, hi):
+    """lo <= x <= hi on the 64-bit column (H, L); bounds are Python ints
+    within +-(10^18 + 1), or None for an open end."""
+    if lo is not None and hi is not None and lo > hi:
+        return ("lt", H, I32_MIN)
+    parts = []
+    lh = ll = hh = hl = None
+    if lo is not None:
+        lh, ll = _words(lo)
+    if hi is not None:
+        hh, hl = _words(hi)
+    if lo is not None and hi is not None and lh == hh:
+        return ("and", [("eq", H, lh), ("between", L, ll, hl)])
+    parts.append(("between", H, lh if lo is not None else I32_MIN, hh if hi is not None else I32_MAX))
+    if lo is not None:    # H > lh or L >= ll
+        parts.append(("or", [("gt", H, lh), ("between", L, ll, I32_MAX)]))
+    if hi is not None:    # H < hh or L <= hl
+        parts.append(("or", [("lt", H, hh), ("between", L, I32_MIN, hl)]))
+    return ("and", parts) if len(parts) > 1 else parts[0]
+
+
+def _decimal64_leaf(scale, L, leaf):
+    op, H = leaf[0], leaf[1]
+    if op == "in":
+        vals = sorted({v for v, e in (decimal_bound(x, scale, esc.EQ) for x in leaf[2]) if not e})
+        if not vals:
+            return ("lt", H, I32_MIN)
+        groups = {}
+        for v in vals:
+            h, lo = _words(v)
+            groups.setdefault(h, []).append(lo)
+        # H in {h} and, for each h, (H != h or L in lows(h))
+        parts = [("in", H, sorted(groups))]
+        for h, lows in sorted(groups.items()):
+            if len(groups) == 1:
+                parts.append(("in", L, lows))
+            else:
+                parts.append(("or", [("lt", H, h), ("gt", H, h), ("in", L, lows)]))
+        return ("and", parts)
+    if op == "eq":
+        v, empty = decimal_bound(leaf[2], scale, esc.EQ)
+        return ("lt", H, I32_MIN) if empty else _range64(H, L, v, v)
+    if op == "lt":
+        return _range64(H, L, None, decimal_bound(leaf[2], scale, esc.LT)[0])
+    if op == "gt":
+        return _range64(H, L, decimal_bound(leaf[2], scale, esc.GT)[0], None)
+    if op == "between":
+        lo = decimal_bound(leaf[2], scale, esc.LT)[0] + 1
+        hi = decimal_bound(leaf[3], scale, esc.GT)[0] - 1
+        return _range64(H, L, lo, hi)
+    raise ValueError(f"{op} is not a decimal comparison")
+
+
 def lower(pred, types):
-    """Rewrites leaves on typed columns; types: {col: ("text", Dict) |
-    ("decimal", scale)}.  Other leaves are kept."""
+    """Rewrites leaves on typed columns; types maps a column to ("text",
+    Dict), ("decimal", scale) (value * 10^scale in int32) or ("decimal64",
+    scale, L) (value * 10^scale in int64 as the word columns H = this
+    column and L, see split_words).  Other leaves are kept."""
     op = pred[0]
     if op in ("and", "or"):
         return (op, [lower(q, types) for q in pred[1]])
     if op == "udf" or pred[1] not in types:
         return pred
-    kind, arg = types[pred[1]]
+    kind, arg = types[pred[1]][0], types[pred[1]][1]
     if kind == "text":
         return _text_leaf(arg, pred)
+    if kind == "decimal64":
+        return _decimal64_leaf(arg, types[pred[1]][2], pred)
     return _decimal_leaf(arg, pred)

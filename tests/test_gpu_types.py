@@ -24,28 +24,40 @@ def ctx():
 
 
 def workload(n, seed):
+    """Columns: TEXT codes, DECIMAL(15,2) price and discount in int32,
+    INTEGER quantity, and a DECIMAL(15,2) column beyond int32 as its two
+    word columns 4 (H) and 5 (L)."""
     vocab, idx, price, disc, qty = dg.typed_columns(n, seed)
+    wide = dg.typed_wide(n, seed + 7)
     text = np.array(vocab, dtype=object)[idx]
     raw = [list(text), [Decimal(int(c)).scaleb(-2) for c in price],
-           [Decimal(int(c)).scaleb(-2) for c in disc], qty]
+           [Decimal(int(c)).scaleb(-2) for c in disc], qty, [Decimal(int(c)).scaleb(-2) for c in wide], None]
     d = types.Dict(vocab)
-    t = dg.Table("typed", n, [dg.INT32] * 4, [d.encode(text), price, disc, qty], ["text", "dec", "dec", "int"],
-                 [None] * 4)
-    return vocab, raw, t, {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2)}
+    hi, lo = types.split_words(wide)
+    t = dg.Table("typed", n, [dg.INT32] * 6, [d.encode(text), price, disc, qty, hi, lo],
+                 ["text", "dec", "dec", "int", "dec64 hi", "dec64 lo"], [None] * 6)
+    return vocab, wide, raw, t, {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2), 4: ("decimal64", 2, 5)}
 
 
-KINDS = ["text", "decimal", "decimal", "int"]
+KINDS = ["text", "decimal", "decimal", "int", "decimal", "int"]
 
 
 @pytest.mark.parametrize("n,seed,npreds", [(0, 31, 10), (1, 32, 20), (4097, 33, 40), (100_003, 34, 60)])
 def test_typed_counts_and_rows(ctx, n, seed, npreds):
     import torch
-    vocab, raw, t, tmap = workload(n, seed)
+    vocab, wide, raw, t, tmap = workload(n, seed)
     dt = esc.device_table(t)
-    preds = dg.typed_preds(vocab, np.random.default_rng(seed + 100), npreds)
+    sample = wide[:1000] if n else dg.typed_wide(1000, seed)
+    preds = dg.typed_preds(vocab, np.random.default_rng(seed + 100), npreds, wide=sample)
+    unsupported = 0
     for i, p in enumerate(preds):
         want = np.flatnonzero(typed.eval_rows(raw, KINDS, p)) if n else np.zeros(0, np.int64)
-        cp = esc.Pred(dt, types.lower(p, tmap))
+        try:
+            cp = esc.Pred(dt, types.lower(p, tmap))
+        except esc.EscError as e:     # rare ORs of several 64-bit decimal ranges exceed the program limits
+            assert e.status == esc.ERR_UNSUPPORTED, (e, p)
+            unsupported += 1
+            continue
         got = ctx.count(dt, cp)
         assert got == len(want), (n, i, p)
         if i % 4 == 0:
@@ -57,3 +69,4 @@ def test_typed_counts_and_rows(ctx, n, seed, npreds):
             ids = rowids[:got].cpu().numpy()
             assert np.array_equal(ids, want), (n, i, p)
             assert np.array_equal(outs[0][:got].cpu().numpy(), t.cols[0][want])
+    assert unsupported <= max(1, npreds // 20)

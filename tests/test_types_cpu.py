@@ -152,28 +152,54 @@ def test_decimal_bound_errors():
 
 # ---------------------------------------------------------------- lowering, end to end on the CPU
 
+def test_word_split_order():
+    x = np.array(sorted(set(dg.WIDE_EDGES + [-2**63, 2**63 - 1, 5, -5, 2**40 + 3])), dtype=np.int64)
+    hi, lo = types.split_words(x)
+    assert np.array_equal(np.lexsort((lo, hi)), np.arange(len(x)))   # (H, L) order = value order
+    assert np.array_equal(hi.astype(np.int64) * 2**32 + (lo.view(np.uint32) ^ 0x80000000), x)
+
+
+def test_range64_brute_force():
+    edges = sorted({e + d for e in dg.WIDE_EDGES for d in (-1, 0, 1)} | {-7 * 2**32 + 5, 3 * 2**32})
+    x = np.array(edges, dtype=np.int64)
+    hi, lo = types.split_words(x)
+    t = dg.Table("w", len(x), [dg.INT32] * 2, [hi, lo], ["h", "l"], [None] * 2)
+    bounds = edges[::2] + [None]
+    for a in bounds:
+        for c in bounds:
+            want = np.ones(len(x), bool)
+            if a is not None:
+                want &= x >= a
+            if c is not None:
+                want &= x <= c
+            got = scan.eval_rows(t, types._range64(0, 1, a, c)).astype(bool)
+            assert np.array_equal(got, want), (a, c)
+
+
 def typed_workload(n, seed):
     vocab, idx, price, disc, qty = dg.typed_columns(n, seed)
+    wide = dg.typed_wide(n, seed + 7)
     text = np.array(vocab, dtype=object)[idx]
     raw = [list(text), [Decimal(int(c)).scaleb(-2) for c in price],
-           [Decimal(int(c)).scaleb(-2) for c in disc], qty]
-    kinds = ["text", "decimal", "decimal", "int"]
-    return vocab, idx, price, disc, qty, raw, kinds
+           [Decimal(int(c)).scaleb(-2) for c in disc], qty, [Decimal(int(c)).scaleb(-2) for c in wide], None]
+    kinds = ["text", "decimal", "decimal", "int", "decimal", "int"]
+    return vocab, idx, price, disc, qty, wide, raw, kinds
 
 
-def lowered_table(vocab, idx, price, disc, qty):
+def lowered_table(vocab, idx, price, disc, qty, wide):
     d = types.Dict(vocab)
     codes = d.encode(np.array(vocab, dtype=object)[idx])
-    t = dg.Table("typed", len(idx), [dg.INT32] * 4, [codes, price, disc, qty], ["text", "dec", "dec", "int"],
-                 [None] * 4)
+    hi, lo = types.split_words(wide)
+    t = dg.Table("typed", len(idx), [dg.INT32] * 6, [codes, price, disc, qty, hi, lo],
+                 ["text", "dec", "dec", "int", "dec64 hi", "dec64 lo"], [None] * 6)
     return d, t
 
 
 def test_lowered_counts_match_typed_oracle():
-    vocab, idx, price, disc, qty, raw, kinds = typed_workload(20_000, 21)
-    d, t = lowered_table(vocab, idx, price, disc, qty)
-    tmap = {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2)}
-    preds = dg.typed_preds(vocab, np.random.default_rng(22), 150)
+    vocab, idx, price, disc, qty, wide, raw, kinds = typed_workload(20_000, 21)
+    d, t = lowered_table(vocab, idx, price, disc, qty, wide)
+    tmap = {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2), 4: ("decimal64", 2, 5)}
+    preds = dg.typed_preds(vocab, np.random.default_rng(22), 200, wide=wide[:1000])
     nonzero = 0
     for p in preds:
         want = typed.eval_rows(raw, kinds, p)
@@ -181,3 +207,22 @@ def test_lowered_counts_match_typed_oracle():
         assert np.array_equal(got.astype(bool), want), p
         nonzero += 0 < want.sum() < len(want)
     assert nonzero > 40      # the workload is not degenerate
+
+
+def test_lowered_predicates_compile():
+    """The lowered typed workload fits the compiled program limits, apart
+    from rare ORs of several 64-bit decimal ranges (each a few clauses, and
+    an OR distributes them)."""
+    vocab, idx, price, disc, qty, wide, raw, kinds = typed_workload(2000, 21)
+    d, t = lowered_table(vocab, idx, price, disc, qty, wide)
+    tmap = {0: ("text", d), 1: ("decimal", 2), 2: ("decimal", 2), 4: ("decimal64", 2, 5)}
+    st = esc.schema_table(t)
+    unsupported = 0
+    preds = dg.typed_preds(vocab, np.random.default_rng(23), 400, wide=wide[:1000])
+    for p in preds:
+        try:
+            esc.Pred(st, types.lower(p, tmap))
+        except esc.EscError as e:
+            assert e.status == esc.ERR_UNSUPPORTED, (e, p)
+            unsupported += 1
+    assert unsupported <= len(preds) // 100
