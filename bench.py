@@ -18,6 +18,7 @@ value = algorithmic bytes of one step / step time, in GB/s:
 Prints one JSON line.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -160,6 +161,8 @@ def main():
     ap.add_argument("--batched", action="store_true", help="batched workload only (256 sub-queries, 8 tables)")
     ap.add_argument("--policy", action="store_true", help="materialization policy: calibrated cost model vs measured costs")
     ap.add_argument("--join", action="store_true", help="star join over ESC temporary tables (10M / 100M build, 1B probe)")
+    ap.add_argument("--sweeps", action="store_true", help="selectivity sweep (2*10^8-row permutation) and "
+                                                               "1..5-attribute sweep (star table)")
     ap.add_argument("--typed", action="store_true", help="TEXT / DECIMAL(15,2) predicates (60M rows, 64 predicates)")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
@@ -178,6 +181,8 @@ def main():
         return join_workload()
     if args.typed:
         return typed_workload()
+    if args.sweeps:
+        return sweeps_workload()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only (sharding by rows across GPUs is designed, "
                                    "not implemented): --gpus must be 1"}))
@@ -872,6 +877,86 @@ def typed_workload(n=60_000_000, npreds=64, sample=200_000):
         "cpu_baseline": {"value": round(nq * sample / osec, 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
                          "sample": f"typed oracle on the first {sample} rows, {nq} predicates",
                          "errors": errors}}), flush=True)
+
+
+def sweeps_workload(n_perm=200_000_000, reps=5):
+    """Synthetic analogs of the paper's selectivity and attribute-count
+    measurements (Section 3, Tables 2 and 3).
+
+    Selectivity: count(A < k) and count + materialize (row ids and A) on a
+    permutation column of 2*10^8 rows for selectivities 10^-5 .. 1; every
+    count must be k exactly and the materialized A values must sum to
+    k(k-1)/2 (closed forms).  Attributes: conjunctions over 1..5 distinct
+    columns of the 60M-row star table, counted; the counts of the first
+    2*10^6 rows must equal the oracle's.  Each timing is the median of
+    `reps` event-timed calls, each after a 1 GiB eviction read."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc
+    from oracle import scan
+    torch.cuda.init()
+    dev = "cuda:0"
+    ctx = esc.Context(0)
+    scratch = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+
+    def timed(fn, fresh_ws=None):
+        out, r = [], None
+        for _ in range(reps):
+            if fresh_ws is not None:     # forget the previous call's tiles: count again inside the timing
+                esc.check(esc.lib().esc_workspace_init(ctx.h, ctypes.c_void_p(fresh_ws.data_ptr()),
+                                                       fresh_ws.numel(), esc._stream_handle(None)))
+            scratch.sum()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            r = fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return r, float(np.median(out))
+
+    log("sweeps: permutation column")
+    A = dg._backend(dg.data_seed(8), dev).perm(n_perm)
+    dt = esc.Table(n_perm, [dg.INT32], [A])
+    rowids = torch.empty(n_perm, dtype=torch.int32, device=dev)
+    aout = torch.empty(n_perm, dtype=torch.int32, device=dev)
+    ws = ctx.workspace(dt)
+    sel_rows, errors = [], 0
+    for sel in (1e-5, 1e-4, 1e-3, 1e-2, 0.1, 0.5, 1.0):
+        k = int(round(sel * n_perm))
+        p = esc.Pred(dt, ("lt", 0, k))
+        c, t_count = timed(lambda: ctx.count(dt, p))
+        m, t_mat = timed(lambda: ctx.materialize(dt, p, [0], rowids, [aout], n_perm, ws=ws), fresh_ws=ws)
+        _, t_write = timed(lambda: ctx.materialize(dt, p, [0], rowids, [aout], n_perm, ws=ws))
+        ok = c == k and m == k and int(aout[:k].to(torch.int64).sum().item()) == k * (k - 1) // 2
+        errors += int(not ok)
+        sel_rows.append({"selectivity": sel, "count": c, "count_ms": round(t_count, 3),
+                         "count_GBps": round(4 * n_perm / (t_count * 1e-3) / 1e9, 1),
+                         "count_materialize_ms": round(t_mat, 3), "materialize_after_count_ms": round(t_write, 3),
+                         "materialize_out_GBps": round(8 * k / (t_mat * 1e-3) / 1e9, 1)})
+    del A, rowids, aout, dt, ws
+    torch.cuda.empty_cache()
+
+    log("sweeps: star table")
+    t = dg.table_star(60_000_000, device=dev)
+    st = esc.Table(t.nrows, t.dtypes, t.cols)
+    pre_n = 2_000_000
+    pre_host = dg.Table("pre", pre_n, t.dtypes, [c[:pre_n].cpu().numpy() for c in t.cols], t.kinds, t.domain)
+    pre_dev = esc.Table(pre_n, t.dtypes, [c[:pre_n] for c in t.cols])
+    leaves = [("between", 2, 10, 30), ("in", 3, [1, 4, 6]), ("lt", 4, np.float32(3000.0)),
+              ("between", 0, dg.DATE_LO + 365, dg.DATE_LO + 1095), ("gt", 5, 150)]
+    attr_rows = []
+    for m in range(1, 6):
+        spec = leaves[0] if m == 1 else ("and", leaves[:m])
+        p = esc.Pred(st, spec)
+        c, tc = timed(lambda: ctx.count(st, p))
+        errors += int(ctx.count(pre_dev, esc.Pred(pre_dev, spec)) != scan.count(pre_host, spec))
+        attr_rows.append({"attributes": m, "count": c, "selectivity": round(c / t.nrows, 6),
+                          "count_ms": round(tc, 3), "GBps": round(4 * m * t.nrows / (tc * 1e-3) / 1e9, 1)})
+    print(json.dumps({
+        "workload": "selectivity sweep on a 2*10^8-row permutation column; 1..5-attribute sweep on the "
+                    "60M-row star table",
+        "selectivity_sweep": sel_rows, "attribute_sweep": attr_rows, "errors": errors}), flush=True)
 
 
 if __name__ == "__main__":

@@ -214,8 +214,9 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
  * `capacity`, the first `capacity` rows are written, *out_count receives the
  * full count and ESC_ERR_CAPACITY is returned.  0 <= nproj <= ESC_MAX_PROJ;
  * dev_rowids may be NULL when only projections are wanted.
- * When the last scan on this workspace was an esc_count of the same table
- * handle and predicate handle (the ESC flow: count, decide, materialize),
+ * When the last scan on this workspace (an esc_count or esc_materialize)
+ * was of the same table handle and predicate handle (the ESC flow: count,
+ * decide, materialize),
  * its per-tile counts and truth masks are reused and the predicate's columns
  * are not read again, only the projected ones; this assumes the table's
  * contents did not change in between (call esc_workspace_init after
