@@ -150,7 +150,7 @@ int esc_ctx_create(int device, esc_ctx **out)
         return hip_fail(e, "hipHostMalloc");
     }
     const char *r = getenv("ESC_COUNT_VARIANT");
-    if (r && atoi(r) >= 0 && atoi(r) <= 3) c->count_variant = atoi(r);
+    if (r && atoi(r) >= 0 && atoi(r) <= 4) c->count_variant = atoi(r);
     r = getenv("ESC_NONTEMPORAL");
     if (r) c->nt = atoi(r) != 0;
     r = getenv("ESC_BLOCKS_PER_CU");
@@ -225,17 +225,17 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
     } else {
         // a workspace with room for the tiles receives them (the shape a
         // materialization reads back); otherwise the plain count's shape
-        const WsLayout Lt = ws_layout(t->nrows, count_rpt(ctx->count_variant, P.nslots, true));
+        const WsLayout Lt = ws_layout(t->nrows, count_rpt(ctx->count_variant, P.nslots, P.ninsn, true));
         const bool tiles = ws_bytes >= Lt.bytes;
         if (!tiles && need_tiles) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, Lt.bytes);
-        const int rpt = count_rpt(ctx->count_variant, P.nslots, tiles);
+        const int rpt = count_rpt(ctx->count_variant, P.nslots, P.ninsn, tiles);
         const WsLayout L = ws_layout(t->nrows, rpt);
         TileOut to{nullptr, nullptr};
         if (tiles) {
             to.counts = (uint32_t *)((char *)dev_ws + L.counts_off);
             to.bits = (uint32_t *)((char *)dev_ws + L.bits_off);
         }
-        CountFn fn = count_fn(P.nslots, ctx->count_variant, (P.flags & P_HAS_UDF) != 0, tiles);
+        CountFn fn = count_fn(P.nslots, P.ninsn, ctx->count_variant, (P.flags & P_HAS_UDF) != 0, tiles);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
         int64_t grid = (int64_t)ctx->num_cus *
                        (ctx->bpc > 0 ? count_bpc(ctx->count_variant, P.nslots, ctx->bpc, tiles) : occ);
@@ -282,7 +282,7 @@ static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *
                               void *dev_ws, size_t ws_bytes, hipStream_t s, unsigned long long *dev_total)
 {
     if (!ctx || !t || !p) return fail(ESC_ERR_INVALID, "null handle");
-    const int rpt = count_rpt(ctx->count_variant, p->prog.nslots, true);
+    const int rpt = count_rpt(ctx->count_variant, p->prog.nslots, p->prog.ninsn, true);
     const WsLayout L = ws_layout(t->nrows, rpt);
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, L.bytes);
     if (rc) return rc;

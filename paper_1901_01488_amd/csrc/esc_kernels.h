@@ -46,8 +46,8 @@ typedef void (*CountFn)(const Program, const ColPtrs, int64_t, WsHeader *, unsig
 typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjArgs, int32_t *, unsigned long long,
                         uint32_t);
 
-CountFn count_fn(int nslots, int variant, bool udf, bool tiles);
-int count_rpt(int variant, int nslots, bool tiles);
+CountFn count_fn(int nslots, int ninsn, int variant, bool udf, bool tiles);
+int count_rpt(int variant, int nslots, int ninsn, bool tiles);
 int count_bpc(int variant, int nslots, int bpc, bool tiles);
 WriteFn write_fn(int rpt);
 typedef void (*ConjFn)(const Program *, int, const ColPtrs, int64_t, unsigned long long *);

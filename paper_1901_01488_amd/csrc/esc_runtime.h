@@ -9,7 +9,7 @@ struct esc_ctx {
     int device = 0;
     int num_cus = 0;
     unsigned long long *pinned = nullptr;   // 4 KiB of pinned host memory for read-backs
-    int count_variant = 3;                  // count kernel shape (see count_rpt / count_bpc)
+    int count_variant = 4;                  // count kernel shape (see count_rpt / count_bpc)
     int nt = 1;                             // streaming loads in the scans
     int bpc = 1;                            // count-kernel blocks per CU (0: occupancy)
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)

@@ -317,23 +317,27 @@ constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 // (one-column counts 5.2 against 4.8), while counts that store tiles keep
 // variant 1 (with 16 rows per lane they store twice the mask bytes and the
 // offset scan has twice the tiles: 154 against 145 us per count).
-int count_rpt(int variant, int k, bool tiles)
+int count_rpt(int variant, int k, int ninsn, bool tiles)
 {
     if (variant == 2) return 8;
     if (variant == 3 && !tiles) return k <= 2 ? 32 : 16;
+    // plain counts of three or more columns: 16 rows per lane when the
+    // program is one test per column; longer programs are interpreted once
+    // per wave tile and keep 32 rows per lane to spread that over more rows
+    if (variant == 4 && !tiles) return k <= 2 || ninsn > k ? 32 : 16;
     return variant == 0 || k > 4 ? 16 : 32;
 }
 
-// blocks of four waves per CU: two for one-column plain counts under variant 3
+// blocks of four waves per CU: two for one-column plain counts under variants 3 and 4
 int count_bpc(int variant, int k, int bpc, bool tiles)
 {
-    return variant == 3 && !tiles && k <= 1 ? 2 * bpc : bpc;
+    return variant >= 3 && !tiles && k <= 1 ? 2 * bpc : bpc;
 }
 
-CountFn count_fn(int k, int variant, bool udf, bool tiles)
+CountFn count_fn(int k, int ninsn, int variant, bool udf, bool tiles)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (count_rpt(variant, k, tiles)) {
+    switch (count_rpt(variant, k, ninsn, tiles)) {
     case 8: return udf ? count_table_impl<8, true>(k, S{}) : count_table_impl<8, false>(k, S{});
     case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
     default: return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
