@@ -128,7 +128,18 @@ int esc_abi_version(void);
 /* ------------------------------------------------------------------ context */
 
 /* Binds HIP device `device`, reads its properties and allocates a small
- * pinned host buffer for results.  ESC_ERR_HIP when the device is absent. */
+ * pinned host buffer for results.  ESC_ERR_HIP when the device is absent.
+ * Kernel-shape settings are read from the environment here, once per
+ * context (all optional; the defaults are the measured best on MI355X):
+ *   ESC_COUNT_VARIANT 0..4   count kernel rows per lane and blocks per CU
+ *                            (4: by column count, program length and use);
+ *   ESC_BLOCKS_PER_CU n      count grid = n blocks per CU (default: occupancy);
+ *   ESC_MAT_BLOCKS_PER_CU n  same for the materialization's write pass;
+ *   ESC_NONTEMPORAL 0|1      non-temporal column loads;
+ *   ESC_DENSE_SHIFT 0..12    write-pass dense threshold 2^-shift (default 7).
+ * Outside the context: ESC_IN_HASH_MIN (compiler: smallest IN-list given a
+ * slot table or bitmap, default 3, 0 = never) and ESC_AUTOTUNE_CACHE (a file
+ * that keeps batched autotuning results between processes). */
 int esc_ctx_create(int device, esc_ctx **out);
 int esc_ctx_destroy(esc_ctx *ctx);
 /* Number of compute units of the context's device. */
