@@ -920,12 +920,13 @@ def sweeps_workload(n_perm=200_000_000, reps=5):
     dt = esc.Table(n_perm, [dg.INT32], [A])
     rowids = torch.empty(n_perm, dtype=torch.int32, device=dev)
     aout = torch.empty(n_perm, dtype=torch.int32, device=dev)
-    ws = ctx.workspace(dt)
+    ws = ctx.workspace(dt)                                # materialization workspace
+    cws = ctx.workspace(dt, False, key="count-only")     # plain counts store no tiles
     sel_rows, errors = [], 0
     for sel in (1e-5, 1e-4, 1e-3, 1e-2, 0.1, 0.5, 1.0):
         k = int(round(sel * n_perm))
         p = esc.Pred(dt, ("lt", 0, k))
-        c, t_count = timed(lambda: ctx.count(dt, p))
+        c, t_count = timed(lambda: ctx.count(dt, p, ws=cws))
         m, t_mat = timed(lambda: ctx.materialize(dt, p, [0], rowids, [aout], n_perm, ws=ws), fresh_ws=ws)
         _, t_write = timed(lambda: ctx.materialize(dt, p, [0], rowids, [aout], n_perm, ws=ws))
         ok = c == k and m == k and int(aout[:k].to(torch.int64).sum().item()) == k * (k - 1) // 2
@@ -934,7 +935,8 @@ def sweeps_workload(n_perm=200_000_000, reps=5):
                          "count_GBps": round(4 * n_perm / (t_count * 1e-3) / 1e9, 1),
                          "count_materialize_ms": round(t_mat, 3), "materialize_after_count_ms": round(t_write, 3),
                          "materialize_out_GBps": round(8 * k / (t_mat * 1e-3) / 1e9, 1)})
-    del A, rowids, aout, dt, ws
+    del A, rowids, aout, dt, ws, cws
+    ctx._ws.clear()
     torch.cuda.empty_cache()
 
     log("sweeps: star table")
@@ -946,10 +948,11 @@ def sweeps_workload(n_perm=200_000_000, reps=5):
     leaves = [("between", 2, 10, 30), ("in", 3, [1, 4, 6]), ("lt", 4, np.float32(3000.0)),
               ("between", 0, dg.DATE_LO + 365, dg.DATE_LO + 1095), ("gt", 5, 150)]
     attr_rows = []
+    sws = ctx.workspace(st, False, key="count-only")
     for m in range(1, 6):
         spec = leaves[0] if m == 1 else ("and", leaves[:m])
         p = esc.Pred(st, spec)
-        c, tc = timed(lambda: ctx.count(st, p))
+        c, tc = timed(lambda: ctx.count(st, p, ws=sws))
         errors += int(ctx.count(pre_dev, esc.Pred(pre_dev, spec)) != scan.count(pre_host, spec))
         attr_rows.append({"attributes": m, "count": c, "selectivity": round(c / t.nrows, 6),
                           "count_ms": round(tc, 3), "GBps": round(4 * m * t.nrows / (tc * 1e-3) / 1e9, 1)})

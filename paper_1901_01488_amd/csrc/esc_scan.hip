@@ -328,10 +328,13 @@ int count_rpt(int variant, int k, int ninsn, bool tiles)
     return variant == 0 || k > 4 ? 16 : 32;
 }
 
-// blocks of four waves per CU: two for one-column plain counts under variants 3 and 4
+// blocks of four waves per CU; one-column counts run two to keep enough
+// loads in flight (variant 3: plain counts only; variant 4: also counts
+// that store tiles)
 int count_bpc(int variant, int k, int bpc, bool tiles)
 {
-    return variant >= 3 && !tiles && k <= 1 ? 2 * bpc : bpc;
+    if (k > 1 || variant < 3 || (tiles && variant == 3)) return bpc;
+    return 2 * bpc;
 }
 
 CountFn count_fn(int k, int ninsn, int variant, bool udf, bool tiles)
