@@ -226,3 +226,30 @@ def test_lowered_predicates_compile():
             assert e.status == esc.ERR_UNSUPPORTED, (e, p)
             unsupported += 1
     assert unsupported <= len(preds) // 100
+
+
+def test_lowering_edge_cases():
+    """Empty and degenerate typed leaves lower to exact int32 leaves."""
+    d = types.Dict(["b", "ba", "c"])
+    text = ["b", "ba", "c", "ba", "b"]
+    dec = [Decimal("1.00"), Decimal("-2.50"), Decimal("0.01"), Decimal("1.00"), Decimal("21474836.47")]
+    wide = [10**15 - 1, -(10**15 - 1), 2**32, 0, -1]
+    hi, lo = types.split_words(np.array(wide, dtype=np.int64))
+    raw = [text, dec, [Decimal(w).scaleb(-2) for w in wide], None]
+    kinds = ["text", "decimal", "decimal", "int"]
+    t = dg.Table("e", 5, [dg.INT32] * 4, [d.encode(text), np.array([100, -250, 1, 100, 2**31 - 1], np.int32), hi, lo],
+                 ["t", "d", "h", "l"], [None] * 4)
+    tmap = {0: ("text", d), 1: ("decimal", 2), 2: ("decimal64", 2, 3)}
+    cases = [
+        ("prefix", 0, ""), ("prefix", 0, "b"), ("prefix", 0, "bb"), ("in", 0, ["zz", "a"]), ("in", 0, ["c", "c"]),
+        ("between", 0, "c", "b"), ("lt", 0, ""), ("gt", 0, "c"), ("eq", 0, "ba"),
+        ("between", 1, "2", "1"), ("in", 1, ["1.001", "7"]), ("in", 1, ["1", "0.010"]), ("eq", 1, "21474836.47"),
+        ("gt", 1, "21474836.47"), ("lt", 1, "-99999999999"), ("gt", 1, "-99999999999.5"),
+        ("eq", 2, "9999999999999.99"), ("lt", 2, "-9999999999999.99"), ("between", 2, "-0.01", "42949672.96"),
+        ("in", 2, ["42949672.96", "-0.01", "0", "3.333"]), ("gt", 2, "1e3".replace("e3", "000")),
+        ("or", [("prefix", 0, "b"), ("eq", 2, "0")]), ("and", [("gt", 1, "0"), ("lt", 2, "1")]),
+    ]
+    for p in cases:
+        want = typed.eval_rows(raw, kinds, p)
+        got = scan.eval_rows(t, types.lower(p, tmap)).astype(bool)
+        assert np.array_equal(got, want), p
