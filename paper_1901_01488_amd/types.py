@@ -2,11 +2,13 @@
 
 Section 3 (Table 3) measures predicates on TEXT and DECIMAL(15,2) columns.
 Here a TEXT column is stored as dictionary codes (rank in the dictionary's
-byte-wise order) and a DECIMAL(p, s) column as value * 10^s in int32; the
-library translates a string or decimal comparison into a code range or an
+byte-wise order) and a DECIMAL(p, s) column as value * 10^s in int32, or,
+when its values exceed int32, in int64 held as two 32-bit word columns
+(split_words); the library translates a string or decimal comparison into a code range or an
 exact int32 bound (esc_dict_range, esc_decimal_bound), and `lower` rewrites
 a predicate description into int32 leaves on the stored values, which the
-ordinary compiler and kernels then evaluate.
+ordinary compiler and kernels then evaluate.  Everything here runs on the
+host; the library's dictionary and decimal routines do the comparisons.
 
 Extra leaf forms on typed columns: ("eq"|"lt"|"gt", c, v), ("between", c,
 a, b), ("in", c, [v...]) with str constants on TEXT columns and decimal
@@ -16,6 +18,7 @@ on TEXT columns.
 from __future__ import annotations
 
 import ctypes
+from decimal import Decimal
 
 import numpy as np
 
@@ -50,12 +53,16 @@ class Dict:
             self.strings.append(out.value.decode())
 
     def encode(self, values):
-        """int32 codes of an array of strings (all in the dictionary)."""
-        sorted_arr = np.array(self.strings, dtype=object)
-        idx = {s: i for i, s in enumerate(sorted_arr)}
-        return np.fromiter((idx[v] for v in values), dtype=np.int32, count=len(values))
+        """int32 codes of a sequence of strings; each must be in the
+        dictionary (KeyError names the first one that is not)."""
+        idx = {s: i for i, s in enumerate(self.strings)}
+        try:
+            return np.fromiter((idx[v] for v in values), dtype=np.int32, count=len(values))
+        except KeyError as e:
+            raise KeyError(f"{e.args[0]!r} is not in the dictionary") from None
 
     def range(self, op, s, s2=None):
+        """Code interval (lo, hi) of esc_dict_range; (0, -1) when empty."""
         lo, hi = ctypes.c_int32(), ctypes.c_int32()
         esc.check(esc.lib().esc_dict_range(self.h, op, _c_str(s), _c_str(s2) if s2 is not None else None,
                                            ctypes.byref(lo), ctypes.byref(hi)))
@@ -68,8 +75,11 @@ class Dict:
 
 
 def decimal_bound(literal, scale, op):
+    """(bound, empty) of esc_decimal_bound for a literal given as a string
+    or a decimal.Decimal (written out in positional notation)."""
+    text = format(literal, "f") if isinstance(literal, Decimal) else str(literal)
     b, e = ctypes.c_int64(), ctypes.c_int()
-    esc.check(esc.lib().esc_decimal_bound(str(literal).encode(), int(scale), op, ctypes.byref(b), ctypes.byref(e)))
+    esc.check(esc.lib().esc_decimal_bound(text.encode(), int(scale), op, ctypes.byref(b), ctypes.byref(e)))
     return b.value, bool(e.value)
 
 
