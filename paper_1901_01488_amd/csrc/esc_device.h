@@ -303,11 +303,23 @@ __device__ __forceinline__ uint32_t valid_bits(int64_t base, int64_t n)
 }
 
 // Sum of a per-lane value over the wave.
+// Sum of x over the 64 lanes of the wave, returned wave-uniform.  Two quad
+// permutations and two rotations by 4 and 8 lanes within each row of 16
+// (DPP operand modifiers: register moves, no LDS round trips) leave every
+// lane with its row's sum; the four row sums are read from lanes 0, 16, 32
+// and 48.  All 64 lanes must be active (every caller runs it under
+// wave-uniform control flow).
 __device__ __forceinline__ uint32_t wave_sum(uint32_t x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    constexpr int kQuadSwapPairs = 0xB1;   // quad_perm [1, 0, 3, 2]
+    constexpr int kQuadSwapHalves = 0x4E;  // quad_perm [2, 3, 0, 1]
+    constexpr int kRowRor4 = 0x124, kRowRor8 = 0x128;
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadSwapPairs, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kQuadSwapHalves, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowRor4, 0xF, 0xF, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kRowRor8, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 0) + (uint32_t)__builtin_amdgcn_readlane((int)x, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)x, 32) + (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
 }
 
 }  // namespace esc
