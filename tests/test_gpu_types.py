@@ -63,10 +63,14 @@ def test_typed_counts_and_rows(ctx, n, seed, npreds):
         if i % 4 == 0:
             cap = max(got, 1)
             rowids = torch.full((cap,), -7, dtype=torch.int32, device="cuda")
-            outs = [torch.zeros(cap, dtype=torch.int32, device="cuda")]
-            c = ctx.materialize(dt, cp, [0], rowids, outs, got)
+            outs = [torch.zeros(cap, dtype=torch.int32, device="cuda") for _ in range(3)]
+            c = ctx.materialize(dt, cp, [0, 4, 5], rowids, outs, got)
             assert c == got
             ids = rowids[:got].cpu().numpy()
             assert np.array_equal(ids, want), (n, i, p)
             assert np.array_equal(outs[0][:got].cpu().numpy(), t.cols[0][want])
+            # the 64-bit decimal, rebuilt from its two projected word columns
+            hi = outs[1][:got].cpu().numpy().astype(np.int64)
+            lo = outs[2][:got].cpu().numpy().view(np.uint32).astype(np.int64) ^ 0x80000000
+            assert np.array_equal(hi * 2**32 + lo, wide[want]), (n, i, p)
     assert unsupported <= max(1, npreds // 20)
