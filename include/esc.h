@@ -229,9 +229,13 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
  * was of the same table handle and predicate handle (the ESC flow: count,
  * decide, materialize),
  * its per-tile counts and truth masks are reused and the predicate's columns
- * are not read again, only the projected ones; this assumes the table's
- * contents did not change in between (call esc_workspace_init after
- * changing them).  Otherwise the call counts first.  Needs a workspace of
+ * are not read again, only the projected ones.  The count writes a
+ * process-unique stamp into the workspace and the reuse happens only if the
+ * workspace still holds it (checked on the device), so memory that was
+ * freed and handed out again at the same address is counted afresh.  The
+ * reuse assumes that neither the table's contents nor the rest of the
+ * workspace were written in between (call esc_workspace_init after changing
+ * them).  Otherwise the call counts first.  Needs a workspace of
  * esc_workspace_size(t, 1, ...) bytes. */
 int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                     const int32_t *proj_cols, int nproj, int32_t *dev_rowids,

@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <map>
@@ -93,27 +94,49 @@ WsLayout ws_layout(int64_t nrows, int rpt)
 
 // Which (table, predicate, tile size) the per-tile counts in a workspace
 // belong to; kept per context, keyed by the workspace address.
+// The record alone cannot tell whether the memory at that address is still
+// the workspace the count wrote (the caller may have freed it and received
+// the same address again): the count also writes a process-unique stamp into
+// the workspace header, and a materialization that reuses the tiles launches
+// the count in checking mode, which recomputes them unless the header still
+// holds the recorded stamp.
 struct TileRecord {
     uint64_t table_id, pred_id;
     int64_t nrows;
     int rpt;
+    unsigned long long stamp;
 };
 
 static std::mutex g_rec_mu;
 static std::map<std::pair<const esc_ctx *, const void *>, TileRecord> g_records;
+static unsigned long long g_next_stamp = 0;
 
-void remember_tiles(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt)
+unsigned long long new_stamp()
 {
     std::lock_guard<std::mutex> g(g_rec_mu);
-    g_records[{ctx, ws}] = TileRecord{t->id, p->id, t->nrows, rpt};
+    if (g_next_stamp == 0) {
+        // distinct across processes sharing a device buffer's history
+        const unsigned long long salt = (unsigned long long)(uintptr_t)&g_next_stamp ^ (unsigned long long)getpid();
+        g_next_stamp = (salt << 24) | 1ull;
+    }
+    return g_next_stamp++;
 }
 
-bool tiles_valid(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt)
+void remember_tiles(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt,
+                    unsigned long long stamp)
+{
+    std::lock_guard<std::mutex> g(g_rec_mu);
+    g_records[{ctx, ws}] = TileRecord{t->id, p->id, t->nrows, rpt, stamp};
+}
+
+// the stamp of the tiles a workspace should hold for (t, p), 0 if none
+unsigned long long tiles_stamp(const esc_ctx *ctx, const void *ws, const esc_table *t, const esc_pred *p, int rpt)
 {
     std::lock_guard<std::mutex> g(g_rec_mu);
     auto it = g_records.find({ctx, ws});
-    return it != g_records.end() && it->second.table_id == t->id && it->second.pred_id == p->id &&
-           it->second.nrows == t->nrows && it->second.rpt == rpt;
+    const bool same = it != g_records.end() && it->second.table_id == t->id && it->second.pred_id == p->id &&
+                      it->second.nrows == t->nrows && it->second.rpt == rpt;
+    return same ? it->second.stamp : 0ull;
 }
 
 void forget_tiles(const esc_ctx *ctx, const void *ws)
@@ -209,8 +232,11 @@ int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream
 
 // Launches the count kernel; stores per-wave-tile counts in the workspace
 // when it has room for them (and remembers for which table and predicate).
+// With expect != 0 (only when the workspace should hold this predicate's
+// tiles) the kernel returns at once if the workspace's stamp equals it.
 static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
-                        hipStream_t s, unsigned long long *dev_out, bool need_tiles)
+                        hipStream_t s, unsigned long long *dev_out, bool need_tiles,
+                        unsigned long long expect = 0ull)
 {
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
     if (rc) return rc;
@@ -230,10 +256,12 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
         if (!tiles && need_tiles) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, Lt.bytes);
         const int rpt = count_rpt(ctx->count_variant, P.nslots, P.ninsn, tiles);
         const WsLayout L = ws_layout(t->nrows, rpt);
-        TileOut to{nullptr, nullptr};
+        TileOut to{nullptr, nullptr, 0ull, 0ull};
         if (tiles) {
             to.counts = (uint32_t *)((char *)dev_ws + L.counts_off);
             to.bits = (uint32_t *)((char *)dev_ws + L.bits_off);
+            to.expect = expect;
+            to.stamp = expect ? expect : new_stamp();
         }
         CountFn fn = count_fn(P.nslots, P.ninsn, ctx->count_variant, (P.flags & P_HAS_UDF) != 0, tiles);
         const int occ = occupancy((const void *)fn, kScanBlock, 0);
@@ -243,7 +271,7 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
         if (grid > blocks_needed) grid = blocks_needed;
         hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
                            (WsHeader *)dev_ws, dev_out, to);
-        if (to.counts) remember_tiles(ctx, dev_ws, t, p, rpt);
+        if (to.counts) remember_tiles(ctx, dev_ws, t, p, rpt, to.stamp);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ESC_OK : hip_fail(e, "count kernel launch");
@@ -308,10 +336,10 @@ static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *
         uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
         uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
         const uint32_t *bits = (const uint32_t *)((char *)dev_ws + L.bits_off);
-        // pass 1: per-wave-tile counts and lane masks, unless the preceding count left them
-        if (!tiles_valid(ctx, dev_ws, t, p, rpt)) {
-            if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true))) return rc;
-        }
+        // pass 1: per-wave-tile counts and lane masks, unless the preceding
+        // count left them (then the launch only checks the workspace's stamp)
+        const unsigned long long expect = tiles_stamp(ctx, dev_ws, t, p, rpt);
+        if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true, expect))) return rc;
         // pass 2: offsets in row order (total in h->result)
         launch_scan(tiles, L.ntiles, offsets, h, s);
         // pass 3: write

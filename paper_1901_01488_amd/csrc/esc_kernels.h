@@ -27,16 +27,25 @@ struct ProjArgs {
 // Per-wave-tile results of a count pass, kept for a materialization:
 // counts[t] = qualifying rows of wave tile t; bits[64 t + l] = lane l's
 // truth mask of tile t (bit r = row slot r).
+// A count that stores tiles writes `stamp` into the workspace header.  With
+// `expect` != 0 the launch first compares the header's stamp with it: when
+// they are equal the tiles of this table and predicate are already in the
+// workspace and every block returns at once.
 struct TileOut {
     uint32_t *counts;
     uint32_t *bits;
+    unsigned long long stamp;
+    unsigned long long expect;
 };
+
+// The count's running word: rows in bits 0..kTotalBits-1, blocks done above
+// (a table has fewer than 2^31 rows, a grid fewer than 2^24 blocks).
+constexpr int kTotalBits = 40;
 
 // first 64 bytes of a scan workspace; per-wave-tile counts and output offsets follow
 struct WsHeader {
-    unsigned long long total;    // count: running sum (reset by the last block)
-    unsigned int ticket;         // count: blocks done (reset by the last block)
-    unsigned int pad0;
+    unsigned long long total;    // count: blocks done << kTotalBits | rows so far (reset by the last block)
+    unsigned long long stamp;    // which count stored the tiles that follow (0: none)
     unsigned long long result;   // the count of the last call
     unsigned long long pad1[5];
 };

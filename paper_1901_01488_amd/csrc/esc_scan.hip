@@ -50,6 +50,9 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
     const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
+    // the workspace already holds this count's tiles: nothing to do (the
+    // stamp is read from a previous launch's write, the same for every block)
+    if (to.expect != 0ull && ws->stamp == to.expect) return;
     const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
     uint32_t cnt = 0;   // per lane
     for (int64_t t = first; t < ntiles; t += step) {
@@ -72,20 +75,20 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     if (threadIdx.x == 0) {
         unsigned long long b = 0;
         for (int w = 0; w < NW; w++) b += s_cnt[w];
-        // Ordering without device fences (a fence here writes back and
-        // invalidates the L2 in every block and cost about 5 % of a launch):
-        // the ticket add takes an operand computed from the value the total
-        // add returned, so it is issued only after that add was performed;
-        // the last block's read of the total is issued only after its own
-        // ticket add returned, so it follows every block's total add.
-        const unsigned long long old = b ? atomicAdd(&ws->total, b) : 0ull;
-        const unsigned tk = atomicAdd(&ws->ticket, 1u + (old == ~0ull ? 1u : 0u));
-        if (tk == gridDim.x - 1) {
-            // last block: every other block's add is visible; publish and reset
-            const unsigned long long tot = atomicAdd(&ws->total, 0ull);
-            *out = tot;
+        // One 64-bit word carries both the running row count (low
+        // kTotalBits bits) and the number of blocks done (high bits), so
+        // each block's contribution is one atomic read-modify-write of one
+        // location.  All such RMWs are totally ordered and each reads the
+        // value left by the previous ones, so the block whose RMW returns
+        // gridDim.x - 1 blocks done has read the sum of every other block:
+        // exact without fences and without any order between two
+        // addresses.  That block publishes the total and resets the word,
+        // so the next launch on the workspace starts from zero.
+        const unsigned long long old = atomicAdd(&ws->total, (1ull << kTotalBits) | b);
+        if ((old >> kTotalBits) == gridDim.x - 1u) {
+            *out = (old & ((1ull << kTotalBits) - 1ull)) + b;
             atomicExch(&ws->total, 0ull);
-            atomicExch(&ws->ticket, 0u);
+            if (to.counts) ws->stamp = to.stamp;
         }
     }
 }
@@ -244,7 +247,6 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
     const int lane = lane_id();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int64_t t = (int64_t)blockIdx.x * NW + wave_id(); t < ntiles; t += step) {
         const uint32_t o0 = offsets[t], o1 = offsets[t + 1];
         if (o0 == o1 || o0 >= cap) continue;   // wave-uniform
@@ -259,8 +261,10 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_
             uint32_t pre = 0, tot = 0;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
+                // set bits of the ballot in the lanes below this one (mbcnt:
+                // no 64-bit shift by a per-lane amount)
                 const uint64_t b = __ballot((nib >> e) & 1u);
-                pre += (uint32_t)__popcll(b & lt);
+                pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, pre));
                 tot += (uint32_t)__popcll(b);
             }
             if (tot == 0) continue;

@@ -346,6 +346,9 @@ class Context:
         ws = self._ws.get(k)
         if ws is None or ws.numel() < nb.value:
             ws = torch.zeros(nb.value, dtype=torch.uint8, device=f"cuda:{self.device}")
+            # a new allocation may sit at the address of a freed workspace:
+            # drop whatever the library remembers about that address
+            check(lib().esc_workspace_init(self.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(), None))
             self._ws[k] = ws
         return ws
 
