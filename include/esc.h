@@ -252,6 +252,28 @@ int esc_materialize_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                           void *const *dev_proj_out, uint64_t capacity,
                           void *dev_ws, size_t ws_bytes, void *stream, uint64_t *dev_count);
 
+/* Allocation-free materialization, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same computation and outputs as
+ * esc_materialize_async, with the workspace taken from a static device
+ * array of ESC_NOALLOC_SCRATCH_BYTES bytes that the library holds on each
+ * device it runs on until the process ends (its address is looked up once
+ * per device by esc_ctx_create).  No device memory is allocated or freed by
+ * this call.  Tables whose materialization workspace exceeds the array
+ * (more than 65,074,176 rows for predicates that read five or more
+ * columns, 130,148,352 otherwise) are rejected with ESC_ERR_CAPACITY and
+ * nothing is enqueued.  Every call on a device shares that device's array:
+ * calls that may overlap in time on one device (different streams, several
+ * host threads, several contexts) race and must be serialized by the
+ * caller.  A call counts first unless the array still holds this table's and
+ * predicate's tiles from this context's previous call (checked on the
+ * device by a stamp, as in esc_materialize). */
+#define ESC_NOALLOC_SCRATCH_BYTES (16u << 20)
+int esc_materialize_noalloc(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+                            const int32_t *proj_cols, int nproj, int32_t *dev_rowids,
+                            void *const *dev_proj_out, uint64_t capacity,
+                            void *stream, uint64_t *dev_count);
+
 /* Split selectivities of a conjunction, from one scan: for a predicate
  * whose root is AND with m children (any other predicate: m = 1),
  * conj_counts[i] = rows that satisfy child i alone and prefix_counts[i] =

@@ -148,6 +148,38 @@ void forget_tiles(const esc_ctx *ctx, const void *ws)
             it = it->first.first == ctx ? g_records.erase(it) : std::next(it);
 }
 
+// Device memory for esc_materialize_noalloc: the workspace of a
+// materialization (header, per-tile counts, offsets, lane masks) lives in
+// this file-scope array, one copy per device, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress
+// returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)ESC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;   // device -> address of its copy of `scratch`
+
+// The address of this device's copy of the scratch array (the device must be
+// current); the first lookup on a device also clears the workspace header.
+static int scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return ESC_OK;
+    }
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    launch_zero((unsigned long long *)ptr, (int64_t)(sizeof(WsHeader) / 8), nullptr);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "clearing the static scratch");
+    g_scratch_addr[device] = ptr;
+    *out = ptr;
+    return ESC_OK;
+}
+
 }  // namespace esc
 
 using namespace esc;
@@ -182,6 +214,11 @@ int esc_ctx_create(int device, esc_ctx **out)
     if (r) c->mat_bpc = atoi(r);
     r = getenv("ESC_DENSE_SHIFT");
     if (r && atoi(r) >= 0 && atoi(r) <= 12) c->dense_shift = atoi(r);
+    if (int rc = scratch_address(device, &c->scratch)) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return rc;
+    }
     *out = c;
     return ESC_OK;
 }
@@ -458,6 +495,21 @@ int esc_materialize_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, c
     if (!dev_count) return fail(ESC_ERR_INVALID, "null dev_count");
     return materialize_launch(ctx, t, p, proj_cols, nproj, dev_rowids, dev_proj_out, capacity, dev_ws, ws_bytes,
                               (hipStream_t)stream, (unsigned long long *)dev_count);
+}
+
+int esc_materialize_noalloc(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const int32_t *proj_cols,
+                            int nproj, int32_t *dev_rowids, void *const *dev_proj_out, uint64_t capacity,
+                            void *stream, uint64_t *dev_count)
+{
+    if (!dev_count) return fail(ESC_ERR_INVALID, "null dev_count");
+    if (!ctx || !t || !p) return fail(ESC_ERR_INVALID, "null handle");
+    if (!ctx->scratch) return fail(ESC_ERR_INVALID, "context has no static scratch");
+    const WsLayout L = ws_layout(t->nrows, count_rpt(ctx->count_variant, p->prog.nslots, p->prog.ninsn, true));
+    if (L.bytes > kStaticScratchBytes)
+        return fail(ESC_ERR_CAPACITY, "%lld rows need %zu bytes of scratch, the static scratch holds %zu",
+                    (long long)t->nrows, L.bytes, kStaticScratchBytes);
+    return materialize_launch(ctx, t, p, proj_cols, nproj, dev_rowids, dev_proj_out, capacity, ctx->scratch,
+                              kStaticScratchBytes, (hipStream_t)stream, (unsigned long long *)dev_count);
 }
 
 }  // extern "C"

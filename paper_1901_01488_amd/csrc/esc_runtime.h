@@ -16,6 +16,7 @@ struct esc_ctx {
     int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
     void *conj_dev = nullptr;               // split selectivities: programs + counters (allocated on first use)
     void *join_dev = nullptr;               // join count (allocated on first use)
+    void *scratch = nullptr;                // this device's static scratch (esc_materialize_noalloc)
 };
 
 namespace esc {

@@ -109,6 +109,7 @@ def lib():
                                 ctypes.c_int),
             "esc_materialize_async": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, vp],
                                       ctypes.c_int),
+            "esc_materialize_noalloc": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, vp], ctypes.c_int),
             "esc_count_conjuncts": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, P(ctypes.c_int)], ctypes.c_int),
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
