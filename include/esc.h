@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 6
+#define ESC_ABI_VERSION 7
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -199,8 +199,14 @@ int esc_pred_get_info(const esc_pred *p, esc_pred_info *out);
  * overlap in time (different streams) need distinct workspaces.  A workspace
  * sized for materialization (materialize = 1; about nrows/4 bytes) also
  * receives, from every esc_count, the qualifying-row count of each tile of
- * rows and the per-row truth values as bit masks. */
-int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes);
+ * rows and the per-row truth values as bit masks.  kind: ESC_WS_COUNT
+ * (esc_count, esc_join_count: 256 bytes), ESC_WS_MATERIALIZE
+ * (esc_materialize; also serves esc_count), ESC_WS_CONJUNCTS
+ * (esc_count_conjuncts: the conjunct programs and counters). */
+#define ESC_WS_COUNT 0
+#define ESC_WS_MATERIALIZE 1
+#define ESC_WS_CONJUNCTS 2
+int esc_workspace_size(const esc_table *t, int kind, size_t *bytes);
 int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream);
 
 /* Exact COUNT(*) of the selection (Section 2: the selectivity sub-query
@@ -281,10 +287,12 @@ int esc_materialize_noalloc(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
  * predicate's count.  Children are compiled separately (constant folding
  * applies per child); together they read at most 8 columns.  m <=
  * ESC_MAX_CONJ and m <= max_out, else ESC_ERR_UNSUPPORTED / ESC_ERR_INVALID;
- * *out_nconj = m.  Uses device memory of the context; blocks until the
+ * *out_nconj = m.  Needs a workspace of esc_workspace_size(t,
+ * ESC_WS_CONJUNCTS) bytes (256-byte aligned, any contents); blocks until the
  * counts are on the host. */
-int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *stream, int max_out,
-                        uint64_t *conj_counts, uint64_t *prefix_counts, int *out_nconj);
+int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
+                        void *stream, int max_out, uint64_t *conj_counts, uint64_t *prefix_counts,
+                        int *out_nconj);
 
 /* ------------------------------------------------------------------ batched
  *
@@ -343,27 +351,60 @@ int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_v
  * bfloat16 MFMA operands, float32 accumulation, float32 master weights and
  * Adam state on the device.  Parameters are exchanged as one float32 array
  * in the order W1[64][256], b1[256], W2[256][256], b2[256], W3[256][256],
- * b3[256], W4[256], b4[1] (ESC_MLP_NPARAMS values, weights [fan_in][fan_out]). */
+ * b3[256], W4[256], b4[1] (ESC_MLP_NPARAMS values, weights [fan_in][fan_out]).
+ *
+ * Memory is the caller's: the state (esc_mlp_state_bytes(), 256-byte
+ * aligned device memory that must outlive the handle) holds the master
+ * weights, the Adam moments and step count, and bfloat16 copies of the
+ * weights; a training workspace (esc_mlp_workspace_bytes(batch), 256-byte
+ * aligned) holds one minibatch's activations and deltas.  Inference needs no
+ * workspace.  The library allocates no device memory here.  Calls on one
+ * handle must not overlap in time. */
 #define ESC_MLP_NPARAMS 148481
-int esc_mlp_create(esc_ctx *ctx, esc_mlp **out);
-int esc_mlp_destroy(esc_mlp *m);
-int esc_mlp_set_params(esc_mlp *m, const float *host_params);   /* also resets Adam */
+size_t esc_mlp_state_bytes(void);
+/* 0 when batch is outside [1, 4096] */
+size_t esc_mlp_workspace_bytes(int batch);
+/* The estimator starts with all parameters zero. */
+int esc_mlp_create(esc_ctx *ctx, void *dev_state, size_t state_bytes, esc_mlp **out);
+int esc_mlp_destroy(esc_mlp *m);   /* the state memory stays the caller's */
+int esc_mlp_set_params(esc_mlp *m, const float *host_params);   /* also resets Adam (moments and step) */
 int esc_mlp_get_params(esc_mlp *m, float *host_params);
+/* The whole training state: parameters, Adam first and second moments
+ * (ESC_MLP_NPARAMS floats each, parameter order) and the number of Adam
+ * steps taken.  get: any output may be NULL.  set: NULL moments mean zero. */
+int esc_mlp_get_state(esc_mlp *m, float *host_params, float *host_adam_m, float *host_adam_v,
+                      int64_t *steps);
+int esc_mlp_set_state(esc_mlp *m, const float *host_params, const float *host_adam_m,
+                      const float *host_adam_v, int64_t steps);
+/* Checkpoint of the whole training state to a file: a header (8-byte magic
+ * "ESCMLP01", uint32 version 1, uint32 parameter count, int64 Adam steps,
+ * uint64 FNV-1a hash of the three arrays), then parameters, first and second
+ * moments as float32 in host byte order.  Training resumed from a checkpoint
+ * continues exactly as without the interruption.  esc_mlp_load rejects a
+ * file of another size, magic, version or parameter count, or whose hash
+ * does not match (ESC_ERR_INVALID; the estimator is then unchanged). */
+int esc_mlp_save(esc_mlp *m, const char *path);
+int esc_mlp_load(esc_mlp *m, const char *path);
 /* yhat[i] for n rows of dev_x (n x 64 float32, device) into dev_yhat. */
 int esc_mlp_predict(esc_mlp *m, const float *dev_x, int64_t n, float *dev_yhat, void *stream);
 /* Training loss: mean over rows of the Huber loss of e = yhat - y with
  * threshold 1/2 (e^2 / 2 for |e| <= 1/2, (|e| - 1/4) / 2 beyond): squared
  * for small ln-selectivity errors, linear for large ones.
- * esc_mlp_gradients: its gradient over the n rows (n <= 4096), written as a
- * flat float32 array in the parameter order into dev_grads. */
+ * esc_mlp_gradients: its gradient over the n rows (1 <= n <= 4096), written
+ * as a flat float32 array in the parameter order into dev_grads (device);
+ * needs a workspace of esc_mlp_workspace_bytes(n).  Blocks until done. */
 int esc_mlp_gradients(esc_mlp *m, const float *dev_x, const float *dev_y, int64_t n,
-                      float *dev_grads, void *stream);
+                      float *dev_grads, void *dev_ws, size_t ws_bytes, void *stream);
 /* Minibatch Adam: `steps` steps; step s uses rows dev_order[s*batch ..
- * (s+1)*batch) of (dev_x, dev_y); batch in [1, 4096].  host_loss, if not
- * NULL, receives the mean loss of each step (steps floats).  Adam betas
- * 0.9 / 0.999, eps 1e-8. */
+ * (s+1)*batch) of (dev_x, dev_y); batch in [1, 4096]; a workspace of
+ * esc_mlp_workspace_bytes(batch).  dev_loss, if not NULL, is device memory
+ * of `steps` floats that receives the mean loss of each step.  Adam betas
+ * 0.9 / 0.999, eps 1e-8; the Adam step count continues across calls.
+ * Deterministic: the same inputs give bit-identical weights.  Blocks until
+ * done. */
 int esc_mlp_train(esc_mlp *m, const float *dev_x, const float *dev_y, const int32_t *dev_order,
-                  int64_t steps, int batch, float lr, void *stream, float *host_loss);
+                  int64_t steps, int batch, float lr, void *dev_ws, size_t ws_bytes, void *stream,
+                  float *dev_loss);
 
 /* Gate (Section 2.1 and 2.2 read as plan-flip tests): route[i] = 1 when the
  * predicted selectivity s = clamp(exp(yhat[i]), 1/n, 1) of a table with
@@ -434,9 +475,13 @@ int esc_hash_build(esc_ctx *ctx, const int32_t *dev_keys, int64_t nkeys, void *d
  * over probe rows i of the product over j of the number of build rows of
  * table j whose key equals probe column key_cols[j] at row i (int32 or
  * date32 columns).  Waits for the result.  The product of one row must fit
- * in 64 bits.  Errors: ESC_ERR_INVALID, ESC_ERR_TYPE (a float32 key column). */
+ * in 64 bits.  The count is reduced in a workspace of at least
+ * esc_workspace_size(probe, ESC_WS_COUNT, ...) bytes (256-byte aligned, any
+ * contents).  Errors: ESC_ERR_INVALID, ESC_ERR_TYPE (a float32 key column),
+ * ESC_ERR_ALIGN / ESC_ERR_OOM (workspace). */
 int esc_join_count(esc_ctx *ctx, const esc_table *probe, const int32_t *key_cols, void *const *dev_tables,
-                   const size_t *table_bytes, int ntables, void *stream, uint64_t *out_count);
+                   const size_t *table_bytes, int ntables, void *dev_ws, size_t ws_bytes, void *stream,
+                   uint64_t *out_count);
 
 /* ------------------------------------------------------------------ materialization policy
  *

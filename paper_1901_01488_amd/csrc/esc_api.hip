@@ -228,8 +228,6 @@ int esc_ctx_destroy(esc_ctx *ctx)
     if (!ctx) return ESC_OK;
     forget_tiles(ctx, nullptr);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    if (ctx->conj_dev) (void)hipFree(ctx->conj_dev);
-    if (ctx->join_dev) (void)hipFree(ctx->join_dev);
     delete ctx;
     return ESC_OK;
 }
@@ -248,11 +246,20 @@ int esc_ctx_dense_fraction(const esc_ctx *ctx, double *out)
     return ESC_OK;
 }
 
-int esc_workspace_size(const esc_table *t, int materialize, size_t *bytes)
+// split selectivities: the conjunct programs, then 2 * kMaxConj counters
+constexpr size_t kConjCountersOff = ((size_t)kMaxConj * sizeof(Program) + 255) & ~(size_t)255;
+constexpr size_t kConjWsBytes = kConjCountersOff + 2 * kMaxConj * sizeof(unsigned long long);
+
+int esc_workspace_size(const esc_table *t, int kind, size_t *bytes)
 {
     if (!t || !bytes) return fail(ESC_ERR_INVALID, "null argument");
-    size_t need = sizeof(WsHeader);
-    if (materialize) need = ws_layout(t->nrows, 8).bytes;   // the smallest wave tile needs the most slots
+    size_t need;
+    switch (kind) {
+    case ESC_WS_COUNT: need = sizeof(WsHeader); break;
+    case ESC_WS_MATERIALIZE: need = ws_layout(t->nrows, 8).bytes; break;   // the smallest wave tile needs the most slots
+    case ESC_WS_CONJUNCTS: need = kConjWsBytes; break;
+    default: return fail(ESC_ERR_INVALID, "workspace kind %d", kind);
+    }
     *bytes = (need + 255) & ~(size_t)255;
     return ESC_OK;
 }
@@ -420,10 +427,12 @@ int esc_materialize(esc_ctx *ctx, const esc_table *t, const esc_pred *p, const i
     return ESC_OK;
 }
 
-int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *stream, int max_out,
-                        uint64_t *conj_counts, uint64_t *prefix_counts, int *out_nconj)
+int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
+                        void *stream, int max_out, uint64_t *conj_counts, uint64_t *prefix_counts, int *out_nconj)
 {
     if (!ctx || !t || !p || !conj_counts || !prefix_counts || !out_nconj) return fail(ESC_ERR_INVALID, "null argument");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(ESC_ERR_ALIGN, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < kConjWsBytes) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, kConjWsBytes);
     if (!t->has_data()) return fail(ESC_ERR_INVALID, "table has no device columns");
     if (p->schema_dtypes != t->dtypes) return fail(ESC_ERR_INVALID, "predicate was compiled for another schema");
     std::vector<Program> progs;
@@ -449,16 +458,10 @@ int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
             q.insn[0] = Insn{T_BITSET, 0, (uint8_t)(F_SINGLE | F_END_CLAUSE), 0, 0, 0, 0};
         }
     if ((rc = set_device(ctx->device))) return rc;
-    const size_t counters_off = (size_t)kMaxConj * sizeof(Program);
-    const size_t bytes = counters_off + 2 * kMaxConj * sizeof(unsigned long long);
     hipError_t e;
-    if (!ctx->conj_dev && (e = hipMalloc(&ctx->conj_dev, bytes)) != hipSuccess) {
-        ctx->conj_dev = nullptr;
-        return fail(ESC_ERR_OOM, "device memory for conjunct counts: %s", hipGetErrorString(e));
-    }
     hipStream_t s = (hipStream_t)stream;
-    Program *d_progs = (Program *)ctx->conj_dev;
-    unsigned long long *d_out = (unsigned long long *)((char *)ctx->conj_dev + counters_off);
+    Program *d_progs = (Program *)dev_ws;
+    unsigned long long *d_out = (unsigned long long *)((char *)dev_ws + kConjCountersOff);
     if ((e = hipMemcpyAsync(d_progs, progs.data(), m * sizeof(Program), hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "upload conjunct programs");
     launch_zero(d_out, 2 * kMaxConj, s);

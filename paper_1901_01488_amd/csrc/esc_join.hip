@@ -169,10 +169,13 @@ int esc_hash_build(esc_ctx *ctx, const int32_t *dev_keys, int64_t nkeys, void *d
 }
 
 int esc_join_count(esc_ctx *ctx, const esc_table *probe, const int32_t *key_cols, void *const *dev_tables,
-                   const size_t *table_bytes, int ntables, void *stream, uint64_t *out_count)
+                   const size_t *table_bytes, int ntables, void *dev_ws, size_t ws_bytes, void *stream,
+                   uint64_t *out_count)
 {
     if (!ctx || !probe || !key_cols || !dev_tables || !table_bytes || !out_count)
         return fail(ESC_ERR_INVALID, "null argument");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(ESC_ERR_ALIGN, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < sizeof(WsHeader)) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, sizeof(WsHeader));
     if (ntables < 1 || ntables > kJoinMaxTables)
         return fail(ESC_ERR_INVALID, "ntables %d outside [1, %d]", ntables, kJoinMaxTables);
     if (!probe->has_data()) return fail(ESC_ERR_INVALID, "probe table has no device columns");
@@ -193,15 +196,8 @@ int esc_join_count(esc_ctx *ctx, const esc_table *probe, const int32_t *key_cols
     int rc = set_device(ctx->device);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long *d_out = (unsigned long long *)ctx->join_dev;
+    unsigned long long *d_out = &((WsHeader *)dev_ws)->result;
     hipError_t e;
-    if (!d_out) {
-        if ((e = hipMalloc(&ctx->join_dev, 256)) != hipSuccess) {
-            ctx->join_dev = nullptr;
-            return fail(ESC_ERR_OOM, "join counter: %s", hipGetErrorString(e));
-        }
-        d_out = (unsigned long long *)ctx->join_dev;
-    }
     launch_zero(d_out, 1, s);
     const int64_t n = probe->nrows;
     if (n > 0) {

@@ -14,8 +14,6 @@ struct esc_ctx {
     int bpc = 1;                            // count-kernel blocks per CU (0: occupancy)
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)
     int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
-    void *conj_dev = nullptr;               // split selectivities: programs + counters (allocated on first use)
-    void *join_dev = nullptr;               // join count (allocated on first use)
     void *scratch = nullptr;                // this device's static scratch (esc_materialize_noalloc)
 };
 

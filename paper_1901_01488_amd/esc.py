@@ -76,7 +76,8 @@ class BatchOpts(ctypes.Structure):
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-ABI_VERSION = 6   # esc.h's ESC_ABI_VERSION for the struct layouts below
+WS_COUNT, WS_MATERIALIZE, WS_CONJUNCTS = 0, 1, 2   # esc_workspace_size kinds
+ABI_VERSION = 7   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -110,20 +111,28 @@ def lib():
             "esc_materialize_async": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, vp],
                                       ctypes.c_int),
             "esc_materialize_noalloc": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, vp], ctypes.c_int),
-            "esc_count_conjuncts": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, P(ctypes.c_int)], ctypes.c_int),
+            "esc_count_conjuncts": ([vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_int, vp, vp, P(ctypes.c_int)],
+                                    ctypes.c_int),
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
             "esc_batch_destroy": ([vp], ctypes.c_int),
             "esc_featurize": ([vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, vp], ctypes.c_int),
-            "esc_mlp_create": ([vp, P(vp)], ctypes.c_int),
+            "esc_mlp_state_bytes": ([], ctypes.c_size_t),
+            "esc_mlp_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
+            "esc_mlp_create": ([vp, vp, ctypes.c_size_t, P(vp)], ctypes.c_int),
             "esc_mlp_destroy": ([vp], ctypes.c_int),
             "esc_mlp_set_params": ([vp, vp], ctypes.c_int),
             "esc_mlp_get_params": ([vp, vp], ctypes.c_int),
+            "esc_mlp_get_state": ([vp, vp, vp, vp, P(i64)], ctypes.c_int),
+            "esc_mlp_set_state": ([vp, vp, vp, vp, i64], ctypes.c_int),
+            "esc_mlp_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+            "esc_mlp_load": ([vp, ctypes.c_char_p], ctypes.c_int),
             "esc_mlp_predict": ([vp, vp, i64, vp, vp], ctypes.c_int),
-            "esc_mlp_gradients": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
-            "esc_mlp_train": ([vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_float, vp, vp], ctypes.c_int),
+            "esc_mlp_gradients": ([vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+            "esc_mlp_train": ([vp, vp, vp, vp, i64, ctypes.c_int, ctypes.c_float, vp, ctypes.c_size_t, vp, vp],
+                              ctypes.c_int),
             "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
             "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
             "esc_ctx_dense_fraction": ([vp, vp], ctypes.c_int),
@@ -136,7 +145,7 @@ def lib():
             "esc_decimal_bound": ([ctypes.c_char_p, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
             "esc_hash_table_bytes": ([i64, vp], ctypes.c_int),
             "esc_hash_build": ([vp, vp, i64, vp, ctypes.c_size_t, vp], ctypes.c_int),
-            "esc_join_count": ([vp, vp, vp, vp, vp, ctypes.c_int, vp, vp], ctypes.c_int),
+            "esc_join_count": ([vp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
             "esc_policy_keep": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
                                 ctypes.c_int),
             "esc_policy_thresholds": ([vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], ctypes.c_int),
@@ -328,8 +337,10 @@ class Context:
         ptrs = (ctypes.c_void_p * len(tables))(*[t.data_ptr() for t in tables])
         sizes = (ctypes.c_size_t * len(tables))(*[t.numel() for t in tables])
         out = ctypes.c_uint64()
+        ws = self.workspace(probe, WS_COUNT, key="count")
         check(lib().esc_join_count(self.h, probe.h, kc.ctypes.data, ptrs, sizes, len(tables),
-                                   _stream_handle(stream), ctypes.byref(out)))
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream),
+                                   ctypes.byref(out)))
         return out.value
 
     def dense_fraction(self):
@@ -338,12 +349,17 @@ class Context:
         check(lib().esc_ctx_dense_fraction(self.h, ctypes.byref(v)))
         return v.value
 
-    def workspace(self, table: Table, materialize=True, key=None):
-        """A zero-filled device workspace big enough for `table` (cached)."""
+    def workspace(self, table: Table, kind=WS_MATERIALIZE, key=None):
+        """A zero-filled device workspace of the given kind (WS_COUNT,
+        WS_MATERIALIZE or WS_CONJUNCTS; a bool means materialize or not) big
+        enough for `table` (cached per key)."""
         import torch
         nb = ctypes.c_size_t()
-        check(lib().esc_workspace_size(table.h, 1 if materialize else 0, ctypes.byref(nb)))
-        k = key if key is not None else "default"
+        check(lib().esc_workspace_size(table.h, int(kind), ctypes.byref(nb)))
+        # counts and materializations share one default workspace (a count
+        # on a materialization-sized workspace leaves its tiles for the next
+        # materialization of the same predicate)
+        k = key if key is not None else ("default" if int(kind) in (WS_COUNT, WS_MATERIALIZE) else ("default", int(kind)))
         ws = self._ws.get(k)
         if ws is None or ws.numel() < nb.value:
             ws = torch.zeros(nb.value, dtype=torch.uint8, device=f"cuda:{self.device}")
@@ -386,8 +402,10 @@ class Context:
         cc = np.zeros(MAX_CONJ, np.uint64)
         pc = np.zeros(MAX_CONJ, np.uint64)
         m = ctypes.c_int()
-        check(lib().esc_count_conjuncts(self.h, table.h, pred.h, _stream_handle(stream), MAX_CONJ,
-                                        cc.ctypes.data, pc.ctypes.data, ctypes.byref(m)))
+        ws = self.workspace(table, WS_CONJUNCTS, key="conjuncts")
+        check(lib().esc_count_conjuncts(self.h, table.h, pred.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream_handle(stream), MAX_CONJ, cc.ctypes.data, pc.ctypes.data,
+                                        ctypes.byref(m)))
         return cc[:m.value].tolist(), pc[:m.value].tolist()
 
     def materialize_async(self, table: Table, pred: Pred, proj, rowids, outs, capacity, dev_count, ws, stream=None):
@@ -520,15 +538,31 @@ def flat_to_params(flat, dims=(64, 256, 256, 256, 1)):
 
 
 class MLP:
-    """The estimator on the device (weights, Adam state and work buffers)."""
+    """The estimator on the device.  Its state (weights, Adam moments, step
+    count, bf16 weight copies) and the training workspace are torch device
+    tensors owned here and handed to the library."""
 
     def __init__(self, ctx: Context, params=None):
+        import torch
         self.ctx = ctx
+        dev = f"cuda:{ctx.device}"
+        self.state = torch.zeros(lib().esc_mlp_state_bytes(), dtype=torch.uint8, device=dev)
+        self._ws = None
         h = ctypes.c_void_p()
-        check(lib().esc_mlp_create(ctx.h, ctypes.byref(h)))
+        check(lib().esc_mlp_create(ctx.h, ctypes.c_void_p(self.state.data_ptr()), self.state.numel(),
+                                   ctypes.byref(h)))
         self.h = h
         if params is not None:
             self.set_params(params)
+
+    def workspace(self, batch):
+        import torch
+        nb = lib().esc_mlp_workspace_bytes(int(batch))
+        if nb == 0:
+            raise EscError(ERR_INVALID, f"batch {batch} outside [1, 4096]")
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=self.state.device)
+        return self._ws
 
     def set_params(self, params):
         flat = params if isinstance(params, np.ndarray) else params_to_flat(params)
@@ -539,6 +573,24 @@ class MLP:
         flat = np.zeros(MLP_NPARAMS, np.float32)
         check(lib().esc_mlp_get_params(self.h, flat.ctypes.data))
         return flat
+
+    def get_state(self):
+        """(params, adam_m, adam_v, steps)"""
+        p, m, v = (np.zeros(MLP_NPARAMS, np.float32) for _ in range(3))
+        st = ctypes.c_int64()
+        check(lib().esc_mlp_get_state(self.h, p.ctypes.data, m.ctypes.data, v.ctypes.data, ctypes.byref(st)))
+        return p, m, v, st.value
+
+    def set_state(self, params, adam_m, adam_v, steps):
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (params, adam_m, adam_v)]
+        check(lib().esc_mlp_set_state(self.h, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                                      int(steps)))
+
+    def save(self, path):
+        check(lib().esc_mlp_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        check(lib().esc_mlp_load(self.h, os.fsencode(path)))
 
     def predict(self, x, out=None, stream=None):
         import torch
@@ -551,16 +603,21 @@ class MLP:
     def gradients(self, x, y, stream=None):
         import torch
         g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+        ws = self.workspace(x.shape[0])
         check(lib().esc_mlp_gradients(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
-                                      x.shape[0], ctypes.c_void_p(g.data_ptr()), _stream_handle(stream)))
+                                      x.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel(), _stream_handle(stream)))
         return g
 
     def train(self, x, y, order, steps, batch, lr=1e-3, stream=None, want_loss=True):
-        loss = np.zeros(max(steps, 1), np.float32)
+        import torch
+        loss = torch.zeros(max(steps, 1), dtype=torch.float32, device=x.device) if want_loss else None
+        ws = self.workspace(batch)
         check(lib().esc_mlp_train(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                   ctypes.c_void_p(order.data_ptr()), steps, batch, float(lr),
-                                  _stream_handle(stream), loss.ctypes.data if want_loss else None))
-        return loss[:steps]
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream),
+                                  ctypes.c_void_p(loss.data_ptr()) if want_loss else None))
+        return loss[:steps].cpu().numpy() if want_loss else np.zeros(0, np.float32)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 30
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    assert L.esc_abi_version() == 6
+    assert L.esc_abi_version() == 7
 
 
 @pytest.fixture(scope="module")
