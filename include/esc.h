@@ -300,8 +300,10 @@ int esc_count_conjuncts(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
  * selection; this runs many such sub-queries at once.  One persistent kernel
  * reads each table's columns once per predicate group and counts every
  * predicate of the group; the whole launch is captured in a hipGraph.
- * The batch allocates its own device memory (work list, programs, counts)
- * and keeps the tables' column pointers. */
+ * The batch keeps the tables' column pointers; its device memory (work
+ * list, programs, counters) is a caller-owned workspace of at least
+ * esc_batch_workspace_size() bytes, 256-byte aligned, that must outlive the
+ * batch (any contents; the batch never frees it). */
 typedef struct {
     int32_t autotune;        /* 1: time candidate configurations at create */
     int32_t block;           /* threads per block (256 or 512); 0 = default */
@@ -309,16 +311,39 @@ typedef struct {
     int32_t group;           /* predicates evaluated per pass over a chunk; 0 = all of the table's */
     int32_t chunk_rows;      /* rows per work item; 0 = about 8 items per block of the grid */
     int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
+    int32_t max_preds;       /* predicates the batch may hold after esc_batch_update; 0 = npreds */
+    int32_t pad;
 } esc_batch_opts;
 
+/* Workspace bytes of a batch of these predicates over these tables: room
+ * for max(npreds, opts->max_preds) predicates and for the work list of every
+ * plan the options (or the autotuner's candidates, and a choice cached for
+ * these tables and predicates) can build.  A later esc_batch_update whose
+ * plan needs a longer work list gets ESC_ERR_OOM.  opts may be NULL
+ * (defaults).  Host only (plans are built, nothing is launched). */
+int esc_batch_workspace_size(esc_ctx *ctx, const esc_table *const *tables, int ntables,
+                             const esc_pred *const *preds, const int32_t *pred_table, int npreds,
+                             const esc_batch_opts *opts, size_t *bytes);
 int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,
                      const esc_pred *const *preds, const int32_t *pred_table, int npreds,
-                     const esc_batch_opts *opts, void *stream, esc_batch **out);
+                     const esc_batch_opts *opts, void *dev_ws, size_t ws_bytes, void *stream,
+                     esc_batch **out);
+/* Loads autotuner choices from a file written by earlier runs (the file that
+ * the ESC_AUTOTUNE_CACHE environment variable names is loaded the same way
+ * at the first autotuned esc_batch_create).  One entry per line: a key and
+ * five integers (block, rows per thread, group, chunk rows, blocks per CU);
+ * entries whose values a batch would not accept (block other than 256,
+ * rows per thread other than 8 or 16, negative group, chunk rows or blocks
+ * per CU) are skipped.  *accepted / *rejected (either may be NULL) count the
+ * lines kept and skipped.  Host only.  Errors: ESC_ERR_INVALID (null path or
+ * unreadable file). */
+int esc_batch_tune_cache_load(const char *path, int *accepted, int *rejected);
 /* New predicates over the same tables: pred_table gives the owner of each
  * (NULL keeps the previous owners, then npreds must not change).  The work
- * list is rebuilt; the captured graph is reused whenever its buffers and
- * counter capacity still fit, so a new predicate set of a similar size costs
- * a few host-to-device copies. */
+ * list is rebuilt; the captured graph is reused whenever its kernel and
+ * grid are unchanged, so a new predicate set costs a few host-to-device
+ * copies.  More predicates than the batch was created for, or a plan whose
+ * work list does not fit the workspace, give ESC_ERR_OOM. */
 int esc_batch_update(esc_batch *b, const esc_pred *const *preds, const int32_t *pred_table, int npreds,
                      void *stream);
 /* Launches the graph and waits; out_counts[i] = exact count of preds[i]. */

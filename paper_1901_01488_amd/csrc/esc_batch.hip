@@ -162,19 +162,17 @@ struct esc_batch {
     std::vector<int> constant;           // 0: scanned; 1: always true; -1: always false or empty table
     esc_batch_opts opts{};
     int nkernel = 0;                     // predicates evaluated by the kernel
-    // device state
+    // device state: fixed regions of the caller's workspace
     BatchGroup *d_groups = nullptr;
     BatchItem *d_items = nullptr;
     Program *d_progs = nullptr;
     int32_t *d_pred_ids = nullptr;
     unsigned long long *d_counts = nullptr;
     unsigned int *d_queue = nullptr;     // [0] next item, [1] number of items
-    size_t cap_counts = 0;               // predicates the counters and the graph cover
-    const void *graph_ptrs[6] = {};      // buffers the captured graph refers to
-    size_t graph_cap = 0;                // counters the captured graph zeroes and copies
+    size_t cap_counts = 0;               // predicates the regions hold (the counters the graph zeroes and copies)
+    size_t cap_items = 0;                // work items the item region holds
     const void *graph_fn = nullptr;      // kernel the captured graph launches
-    size_t cap_groups = 0, cap_items = 0, cap_progs = 0, cap_ids = 0;
-    unsigned long long *h_counts = nullptr;   // pinned
+    unsigned long long *h_counts = nullptr;   // pinned host memory, cap_counts entries
     int nitems = 0;
     int grid = 0;
     hipGraph_t graph = nullptr;
@@ -277,18 +275,36 @@ int build_plan(const esc_batch *b, const esc_batch_opts &o, int grid, Plan &plan
     return ESC_OK;
 }
 
-template <typename T>
-int ensure(T *&ptr, size_t &cap, size_t n)
+// Regions of a batch workspace for pcap predicates and icap work items.
+struct BatchLayout {
+    size_t queue, counts, ids, progs, groups, items, bytes;
+};
+
+BatchLayout batch_layout(size_t pcap, size_t icap)
 {
-    if (n <= cap && ptr) return ESC_OK;
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    cap = 0;
-    const size_t m = std::max<size_t>(n, 1);
-    hipError_t e = hipMalloc((void **)&ptr, m * sizeof(T));
-    if (e != hipSuccess) return fail(ESC_ERR_OOM, "hipMalloc of %zu bytes: %s", m * sizeof(T), hipGetErrorString(e));
-    cap = m;
-    return ESC_OK;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    BatchLayout L;
+    L.queue = 0;
+    L.counts = 256;
+    L.ids = up(L.counts + pcap * sizeof(unsigned long long));
+    L.progs = up(L.ids + pcap * sizeof(int32_t));
+    L.groups = up(L.progs + pcap * sizeof(Program));
+    L.items = up(L.groups + pcap * sizeof(BatchGroup));
+    L.bytes = up(L.items + icap * sizeof(BatchItem));
+    return L;
+}
+
+// Options as a batch uses them: rows per thread 8 or 16, block of 256.
+esc_batch_opts normalized(const esc_batch_opts *opts)
+{
+    esc_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.rows_per_thread != 16) o.rows_per_thread = 8;
+    o.block = kScanBlock;
+    if (o.group < 0) o.group = 0;
+    if (o.chunk_rows < 0) o.chunk_rows = 0;
+    if (o.blocks_per_cu < 0) o.blocks_per_cu = 0;
+    return o;
 }
 
 void destroy_graph(esc_batch *b)
@@ -303,36 +319,69 @@ void destroy_graph(esc_batch *b)
 // graph of an earlier plan still fits (same buffers, kernel shape and counter
 // capacity): the item count lives in device memory, so a new plan of the
 // same shape costs a few small copies and no capture.
-int install(esc_batch *b, const esc_batch_opts &o)
+// The kernel a batch launches: rows per thread, and udf support when any
+// scanned predicate has a udf.
+BatchFn batch_kernel_for(const esc_batch *b, const esc_batch_opts &o)
 {
     bool udf = false;
     for (size_t p = 0; p < b->src.size(); p++) udf |= b->constant[p] == 0 && (b->src[p].flags & P_HAS_UDF) != 0;
-    BatchFn fn = batch_fn(o.rows_per_thread, udf);
-    const int occ = occupancy((const void *)fn, kScanBlock, 0);
+    return batch_fn(o.rows_per_thread, udf);
+}
+
+// Persistent grid of a launch: blocks per CU as asked, at most what fits
+// (idle blocks exit at once).
+int plan_grid(const esc_batch *b, const esc_batch_opts &o)
+{
+    const int occ = occupancy((const void *)batch_kernel_for(b, o), kScanBlock, 0);
     const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, occ) : occ;
-    const int grid = std::max(1, b->ctx->num_cus * bpc);   // persistent; idle blocks exit at once
+    return std::max(1, b->ctx->num_cus * bpc);
+}
+
+std::string tune_key(const esc_batch *b);
+bool cached_tune(const std::string &key, esc_batch_opts *out);
+
+// The configurations a batch with these options may install: the options
+// themselves, or with autotuning every candidate the tuner times (rows per
+// thread x group size x chunk length) and a choice cached for these tables
+// and predicates.
+std::vector<esc_batch_opts> tuner_candidates()
+{
+    std::vector<esc_batch_opts> out;
+    const int rpts[] = {16, 8};
+    const int groups[] = {0, 16, 8};
+    const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
+    for (int rpt : rpts)
+        for (int grp : groups)
+            for (int ch : chunks) {
+                esc_batch_opts c{};
+                c.block = kScanBlock;
+                c.rows_per_thread = rpt;
+                c.group = grp;
+                c.chunk_rows = ch;
+                out.push_back(c);
+            }
+    return out;
+}
+
+std::vector<esc_batch_opts> candidates(const esc_batch *b, const esc_batch_opts &o)
+{
+    if (!o.autotune) return {o};
+    std::vector<esc_batch_opts> out = tuner_candidates();
+    esc_batch_opts cached{};
+    if (cached_tune(tune_key(b), &cached)) out.push_back(cached);
+    return out;
+}
+
+int install(esc_batch *b, const esc_batch_opts &o)
+{
+    BatchFn fn = batch_kernel_for(b, o);
+    const int grid = plan_grid(b, o);
     Plan plan;
     int rc = build_plan(b, o, grid, plan);
     if (rc) return rc;
-    if ((rc = ensure(b->d_groups, b->cap_groups, plan.groups.size()))) return rc;
-    if ((rc = ensure(b->d_items, b->cap_items, plan.items.size()))) return rc;
-    if ((rc = ensure(b->d_progs, b->cap_progs, plan.progs.size()))) return rc;
-    if ((rc = ensure(b->d_pred_ids, b->cap_ids, plan.pred_ids.size()))) return rc;
-    const size_t npreds = b->pred_table.size();
-    if (npreds > b->cap_counts) {
-        const size_t cap = std::max(npreds, b->cap_counts * 3 / 2);
-        if (b->d_counts) (void)hipFree(b->d_counts);
-        if (b->h_counts) (void)hipHostFree(b->h_counts);
-        b->d_counts = nullptr;
-        b->h_counts = nullptr;
-        b->cap_counts = 0;
-        hipError_t e;
-        if ((e = hipMalloc((void **)&b->d_counts, cap * sizeof(unsigned long long))) != hipSuccess ||
-            (e = hipHostMalloc((void **)&b->h_counts, cap * sizeof(unsigned long long), hipHostMallocDefault)) !=
-                hipSuccess)
-            return fail(ESC_ERR_OOM, "batch counters: %s", hipGetErrorString(e));
-        b->cap_counts = cap;
-    }
+    if (plan.items.size() > b->cap_items)
+        return fail(ESC_ERR_OOM, "the plan has %zu work items, the workspace holds %zu", plan.items.size(),
+                    b->cap_items);
     hipStream_t s = b->cap_stream;
     const unsigned int nitems = (unsigned int)plan.items.size();
     if ((rc = hipchk(hipMemcpyAsync(b->d_groups, plan.groups.data(), plan.groups.size() * sizeof(BatchGroup),
@@ -348,13 +397,10 @@ int install(esc_batch *b, const esc_batch_opts &o)
     if ((rc = hipchk(hipStreamSynchronize(s), "upload sync"))) return rc;
     b->nitems = (int)nitems;
     b->opts = o;
-    b->opts.blocks_per_cu = bpc;
-    // the graph bakes in these buffers, the counter capacity (zeroed and copied
-    // back) and the kernel; a buffer that was reallocated may come back at the
-    // same address with another size, so the capacity is compared too
-    const void *ptrs[6] = {b->d_groups, b->d_items, b->d_progs, b->d_pred_ids, b->d_counts, b->h_counts};
-    const bool reuse = b->exec && grid == b->grid && b->graph_fn == (const void *)fn &&
-                       b->graph_cap == b->cap_counts && memcmp(ptrs, b->graph_ptrs, sizeof ptrs) == 0;
+    b->opts.blocks_per_cu = grid / std::max(1, b->ctx->num_cus);
+    // the graph bakes in the workspace regions (fixed for the batch's
+    // lifetime), the counter capacity and the kernel
+    const bool reuse = b->exec && grid == b->grid && b->graph_fn == (const void *)fn;
     if (reuse) return ESC_OK;
     destroy_graph(b);
     b->grid = grid;
@@ -370,9 +416,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     if (e != hipSuccess) return hip_fail(e, "end capture");
     b->graph = g;
     if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "instantiate");
-    memcpy(b->graph_ptrs, ptrs, sizeof ptrs);
     b->graph_fn = (const void *)fn;
-    b->graph_cap = b->cap_counts;
     return ESC_OK;
 }
 
@@ -407,21 +451,50 @@ std::string tune_key(const esc_batch *b)
     return k;
 }
 
+// Whether cached options are ones a batch would accept as they are.
+bool acceptable(const esc_batch_opts &o)
+{
+    return o.block == kScanBlock && (o.rows_per_thread == 8 || o.rows_per_thread == 16) && o.group >= 0 &&
+           o.chunk_rows >= 0 && o.blocks_per_cu >= 0;
+}
+
+// Reads "key block rpt group chunk bpc" lines into the in-process cache;
+// lines that do not parse or hold options a batch would not accept are
+// skipped.  Needs g_tune_mu.
+int read_tune_file(const char *path, int *accepted, int *rejected)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(ESC_ERR_INVALID, "cannot open %s", path);
+    int ok = 0, bad = 0;
+    char line[8192];
+    while (fgets(line, sizeof line, f)) {
+        char key[4096];
+        esc_batch_opts o{};
+        char extra[2];
+        const int n = sscanf(line, "%4095s %d %d %d %d %d %1s", key, &o.block, &o.rows_per_thread, &o.group,
+                             &o.chunk_rows, &o.blocks_per_cu, extra);
+        if (n <= 0) continue;   // blank line
+        if (n == 6 && acceptable(o)) {
+            g_tune_cache[key] = o;
+            ok++;
+        } else {
+            bad++;
+        }
+    }
+    fclose(f);
+    if (accepted) *accepted = ok;
+    if (rejected) *rejected = bad;
+    return ESC_OK;
+}
+
 void load_tune_file()
 {
     static bool done = false;
     if (done) return;
     done = true;
     const char *path = getenv("ESC_AUTOTUNE_CACHE");
-    if (!path) return;
-    FILE *f = fopen(path, "r");
-    if (!f) return;
-    char key[4096];
-    esc_batch_opts o{};
-    while (fscanf(f, "%4095s %d %d %d %d %d", key, &o.block, &o.rows_per_thread, &o.group, &o.chunk_rows,
-                  &o.blocks_per_cu) == 6)
-        g_tune_cache[key] = o;
-    fclose(f);
+    if (path) (void)read_tune_file(path, nullptr, nullptr);
+    clear_error();
 }
 
 void save_tune(const std::string &key, const esc_batch_opts &o)
@@ -433,6 +506,16 @@ void save_tune(const std::string &key, const esc_batch_opts &o)
     fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
             o.blocks_per_cu);
     fclose(f);
+}
+
+bool cached_tune(const std::string &key, esc_batch_opts *out)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    *out = it->second;
+    return true;
 }
 
 // Times candidate plans on the batch's own tables and keeps the fastest;
@@ -455,17 +538,7 @@ int autotune(esc_batch *b, hipStream_t s)
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ESC_ERR_HIP, "hipEventCreate failed");
     int rc = ESC_OK;
-    const int rpts[] = {16, 8};
-    const int groups[] = {0, 16, 8};
-    const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
-    for (int rpt : rpts)
-        for (int grp : groups)
-            for (int ch : chunks) {
-                esc_batch_opts o{};
-                o.block = kScanBlock;
-                o.rows_per_thread = rpt;
-                o.group = grp;
-                o.chunk_rows = ch;
+    for (const esc_batch_opts &o : tuner_candidates()) {
                 if ((rc = install(b, o))) goto done;
                 if ((rc = run(b, s, got.data()))) goto done;
                 if (!have_ref) { ref = got; have_ref = true; }
@@ -514,12 +587,6 @@ int set_preds(esc_batch *b, const esc_pred *const *preds, int npreds)
 void free_batch(esc_batch *b)
 {
     destroy_graph(b);
-    if (b->d_groups) (void)hipFree(b->d_groups);
-    if (b->d_items) (void)hipFree(b->d_items);
-    if (b->d_progs) (void)hipFree(b->d_progs);
-    if (b->d_pred_ids) (void)hipFree(b->d_pred_ids);
-    if (b->d_counts) (void)hipFree(b->d_counts);
-    if (b->d_queue) (void)hipFree(b->d_queue);
     if (b->h_counts) (void)hipHostFree(b->h_counts);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -529,18 +596,58 @@ void free_batch(esc_batch *b)
 
 extern "C" {
 
+int esc_batch_workspace_size(esc_ctx *ctx, const esc_table *const *tables, int ntables,
+                             const esc_pred *const *preds, const int32_t *pred_table, int npreds,
+                             const esc_batch_opts *opts, size_t *bytes)
+{
+    if (!ctx || !tables || !preds || !pred_table || !bytes) return fail(ESC_ERR_INVALID, "null argument");
+    if (ntables <= 0 || npreds <= 0) return fail(ESC_ERR_INVALID, "empty batch");
+    esc_batch tmp;   // host side only: the plans of these predicates
+    tmp.ctx = ctx;
+    for (int t = 0; t < ntables; t++) {
+        if (!tables[t]) return fail(ESC_ERR_INVALID, "table %d is null", t);
+        tmp.tables.push_back({tables[t]->nrows, tables[t]->dtypes, tables[t]->cols});
+    }
+    for (int p = 0; p < npreds; p++)
+        if (pred_table[p] < 0 || pred_table[p] >= ntables) return fail(ESC_ERR_INVALID, "pred_table[%d] out of range", p);
+    tmp.pred_table.assign(pred_table, pred_table + npreds);
+    int rc = set_preds(&tmp, preds, npreds);
+    if (rc) return rc;
+    const esc_batch_opts o = normalized(opts);
+    size_t items = 0;
+    for (const esc_batch_opts &c : candidates(&tmp, o)) {
+        Plan plan;
+        if ((rc = build_plan(&tmp, c, plan_grid(&tmp, c), plan))) return rc;
+        items = std::max(items, plan.items.size());
+    }
+    *bytes = batch_layout((size_t)std::max(npreds, o.max_preds), items).bytes;
+    return ESC_OK;
+}
+
+int esc_batch_tune_cache_load(const char *path, int *accepted, int *rejected)
+{
+    if (!path) return fail(ESC_ERR_INVALID, "null path");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return read_tune_file(path, accepted, rejected);
+}
+
 int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, const esc_pred *const *preds,
-                     const int32_t *pred_table, int npreds, const esc_batch_opts *opts, void *stream,
-                     esc_batch **out)
+                     const int32_t *pred_table, int npreds, const esc_batch_opts *opts, void *dev_ws,
+                     size_t ws_bytes, void *stream, esc_batch **out)
 {
     if (!ctx || !tables || !preds || !pred_table || !out) return fail(ESC_ERR_INVALID, "null argument");
     if (ntables <= 0 || npreds <= 0) return fail(ESC_ERR_INVALID, "empty batch");
+    if (!dev_ws || ((uintptr_t)dev_ws & 255)) return fail(ESC_ERR_ALIGN, "workspace must be non-null and 256-byte aligned");
+    const esc_batch_opts o = normalized(opts);
+    size_t need = 0;
+    int rc = esc_batch_workspace_size(ctx, tables, ntables, preds, pred_table, npreds, &o, &need);
+    if (rc) return rc;
+    if (ws_bytes < need) return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     esc_batch *b = new (std::nothrow) esc_batch;
     if (!b) return fail(ESC_ERR_OOM, "out of host memory");
     b->ctx = ctx;
     b->device = ctx->device;
     if (int rc0 = set_device(ctx->device)) { delete b; return rc0; }
-    int rc = ESC_OK;
     for (int t = 0; t < ntables; t++) {
         if (!tables[t] || !tables[t]->has_data()) { free_batch(b); return fail(ESC_ERR_INVALID, "table %d has no device columns", t); }
         b->tables.push_back({tables[t]->nrows, tables[t]->dtypes, tables[t]->cols});
@@ -549,17 +656,27 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables, 
     for (int p = 0; p < npreds; p++)
         if (pred_table[p] < 0 || pred_table[p] >= ntables) { free_batch(b); return fail(ESC_ERR_INVALID, "pred_table[%d] out of range", p); }
     if ((rc = set_preds(b, preds, npreds))) { free_batch(b); return rc; }
+    // fixed regions of the workspace: counters and programs for pcap
+    // predicates, the rest of it for work items
+    const size_t pcap = (size_t)std::max(npreds, o.max_preds);
+    const BatchLayout L0 = batch_layout(pcap, 0);
+    char *base = (char *)dev_ws;
+    b->d_queue = (unsigned int *)(base + L0.queue);
+    b->d_counts = (unsigned long long *)(base + L0.counts);
+    b->d_pred_ids = (int32_t *)(base + L0.ids);
+    b->d_progs = (Program *)(base + L0.progs);
+    b->d_groups = (BatchGroup *)(base + L0.groups);
+    b->d_items = (BatchItem *)(base + L0.items);
+    b->cap_counts = pcap;
+    b->cap_items = (ws_bytes - L0.items) / sizeof(BatchItem);
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) { free_batch(b); return hip_fail(e, "stream"); }
-    if ((e = hipMalloc((void **)&b->d_queue, 256)) != hipSuccess) {
+    if ((e = hipHostMalloc((void **)&b->h_counts, pcap * sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess) {
+        b->h_counts = nullptr;
         free_batch(b);
-        return fail(ESC_ERR_OOM, "batch allocation: %s", hipGetErrorString(e));
+        return fail(ESC_ERR_OOM, "pinned host counters: %s", hipGetErrorString(e));
     }
-    esc_batch_opts o{};
-    if (opts) o = *opts;
-    if (o.rows_per_thread != 16) o.rows_per_thread = 8;
-    o.block = kScanBlock;
-    if (opts && opts->autotune) rc = autotune(b, (hipStream_t)stream);
+    if (o.autotune) rc = autotune(b, (hipStream_t)stream);
     else rc = install(b, o);
     if (rc) { free_batch(b); return rc; }
     *out = b;
@@ -574,6 +691,8 @@ int esc_batch_update(esc_batch *b, const esc_pred *const *preds, const int32_t *
     if (!pred_table && npreds != (int)b->pred_table.size())
         return fail(ESC_ERR_INVALID, "a different number of predicates needs pred_table");
     if (int rc0 = set_device(b->device)) return rc0;
+    if ((size_t)npreds > b->cap_counts)
+        return fail(ESC_ERR_OOM, "%d predicates, the batch was created for at most %zu", npreds, b->cap_counts);
     if (pred_table) {
         for (int p = 0; p < npreds; p++)
             if (pred_table[p] < 0 || pred_table[p] >= (int)b->tables.size())

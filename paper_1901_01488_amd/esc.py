@@ -73,7 +73,8 @@ class CostModel(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("max_preds", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 WS_COUNT, WS_MATERIALIZE, WS_CONJUNCTS = 0, 1, 2   # esc_workspace_size kinds
@@ -113,7 +114,11 @@ def lib():
             "esc_materialize_noalloc": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, vp], ctypes.c_int),
             "esc_count_conjuncts": ([vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_int, vp, vp, P(ctypes.c_int)],
                                     ctypes.c_int),
-            "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, P(vp)], ctypes.c_int),
+            "esc_batch_workspace_size": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts),
+                                          P(ctypes.c_size_t)], ctypes.c_int),
+            "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, ctypes.c_size_t, vp,
+                                  P(vp)], ctypes.c_int),
+            "esc_batch_tune_cache_load": ([ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_int)], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
@@ -441,20 +446,33 @@ def schema_table(t):
 
 class Batch:
     """Batched COUNT(*) of many predicates over several tables (one hipGraph
-    launch of a persistent kernel)."""
+    launch of a persistent kernel).  Its device workspace is a torch tensor
+    owned here; an update whose plan no longer fits it re-creates the batch
+    on a larger one."""
 
     def __init__(self, ctx: Context, tables, preds, owner, autotune=False, rows_per_thread=0, group=0,
-                 chunk_rows=0, blocks_per_cu=0, stream=None):
+                 chunk_rows=0, blocks_per_cu=0, max_preds=0, stream=None):
         self.ctx = ctx
         self.tables = list(tables)
+        self._o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu,
+                            max_preds, 0)
+        self.h = None
+        self._create(preds, owner, stream)
+
+    def _create(self, preds, owner, stream, headroom=1.0):
+        import torch
         self.preds = list(preds)
-        self.owner = np.asarray(owner, np.int32)
+        self.owner = np.ascontiguousarray(owner, np.int32)
         th = (ctypes.c_void_p * len(self.tables))(*[t.h for t in self.tables])
         ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
-        o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu)
+        nb = ctypes.c_size_t()
+        check(lib().esc_batch_workspace_size(self.ctx.h, th, len(self.tables), ph, self.owner.ctypes.data,
+                                             len(self.preds), ctypes.byref(self._o), ctypes.byref(nb)))
+        self.ws = torch.empty(int(nb.value * headroom) + 256, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
         h = ctypes.c_void_p()
-        check(lib().esc_batch_create(ctx.h, th, len(self.tables), ph, self.owner.ctypes.data, len(self.preds),
-                                     ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
+        check(lib().esc_batch_create(self.ctx.h, th, len(self.tables), ph, self.owner.ctypes.data, len(self.preds),
+                                     ctypes.byref(self._o), ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                     _stream_handle(stream), ctypes.byref(h)))
         self.h = h
 
     def count(self, stream=None):
@@ -463,12 +481,19 @@ class Batch:
         return out
 
     def update(self, preds, owner=None, stream=None):
+        owner = self.owner if owner is None else np.ascontiguousarray(owner, np.int32)
+        ph = (ctypes.c_void_p * len(preds))(*[p.h for p in preds])
+        rc = lib().esc_batch_update(self.h, ph, owner.ctypes.data, len(preds), _stream_handle(stream))
+        if rc == ERR_OOM:
+            # more predicates or work items than the workspace holds: a new
+            # batch (same options; a tuned choice stays cached) on a larger one
+            lib().esc_batch_destroy(self.h)
+            self.h = None
+            self._create(preds, owner, stream, headroom=1.5)
+            return
+        check(rc)
         self.preds = list(preds)
-        ph = (ctypes.c_void_p * len(self.preds))(*[p.h for p in self.preds])
-        if owner is not None:
-            self.owner = np.ascontiguousarray(owner, np.int32)
-        check(lib().esc_batch_update(self.h, ph, self.owner.ctypes.data if owner is not None else None,
-                                     len(self.preds), _stream_handle(stream)))
+        self.owner = owner
 
     def opts(self):
         o = BatchOpts()

@@ -219,3 +219,25 @@ def test_in_slot_tables(schema, monkeypatch):
     monkeypatch.setenv("ESC_IN_HASH_MIN", "0")
     assert info(pred)["nhashed"] == 0
     assert info(("in", 0, [5, 1000, 77777]))["nhashed"] == 0
+
+
+def test_autotune_cache_file_skips_bad_entries(tmp_path):
+    """Tuning-cache lines whose options a batch would not accept (rows per
+    thread other than 8 or 16, a block other than 256, negative group, chunk
+    or blocks per CU, missing or extra fields) are skipped, not installed."""
+    L = esc.lib()
+    f = tmp_path / "tune.txt"
+    f.write_text("k1 256 16 0 0 0\n"
+                 "k2 256 0 16 131072 2\n"       # rows per thread 0 (a division by zero when planning)
+                 "k3 256 8 -1 0 0\n"
+                 "k4 512 8 0 0 0\n"
+                 "k5 256 8 0 -5 0\n"
+                 "k6 256 16 8 1048576 -1\n"
+                 "junk\n"
+                 "\n"
+                 "k7 256 8 16 131072 2\n"
+                 "k8 256 8 0 0 0 9\n")
+    acc, rej = ctypes.c_int(-1), ctypes.c_int(-1)
+    assert L.esc_batch_tune_cache_load(str(f).encode(), ctypes.byref(acc), ctypes.byref(rej)) == esc.OK
+    assert (acc.value, rej.value) == (2, 7)
+    assert L.esc_batch_tune_cache_load(str(tmp_path / "missing").encode(), None, None) == esc.ERR_INVALID

@@ -114,9 +114,9 @@ def test_batched_update_changes_shape(ctx, small_batch):
 
 
 def test_batched_update_growing_counters(ctx, small_batch):
-    """Each step needs more counters than the last (the counter buffers are
-    reallocated every time, possibly at the same address with a larger size):
-    the launch graph must zero and copy back all of them."""
+    """Each step needs more counters than the last: beyond the predicates the
+    batch was created for the binding re-creates it on a larger workspace;
+    within them the captured graph must zero and copy back every counter."""
     tabs, preds, owner = small_batch
     dts = [esc.device_table(t) for t in tabs]
     cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
@@ -127,3 +127,21 @@ def test_batched_update_growing_counters(ctx, small_batch):
         pick = rng.choice(len(preds), size, replace=False)
         b.update([cps[i] for i in pick], [owner[i] for i in pick])
         assert b.count().tolist() == [want_all[i] for i in pick], size
+
+
+def test_batched_update_beyond_capacity_is_refused(ctx, small_batch):
+    """Through the C ABI, an update with more predicates than the batch was
+    created for (max_preds) is refused with ESC_ERR_OOM and the batch keeps
+    counting its previous predicates exactly."""
+    import ctypes
+    tabs, preds, owner = small_batch
+    dts = [esc.device_table(t) for t in tabs]
+    cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    b = esc.Batch(ctx, dts, cps[:8], owner[:8], max_preds=12)
+    want8 = [scan.count(tabs[o], p) for p, o in zip(preds[:8], owner[:8])]
+    ph = (ctypes.c_void_p * 13)(*[p.h for p in cps[:13]])
+    ow = np.ascontiguousarray(owner[:13], np.int32)
+    assert esc.lib().esc_batch_update(b.h, ph, ow.ctypes.data, 13, None) == esc.ERR_OOM
+    assert b.count().tolist() == want8
+    b.update(cps[:12], owner[:12])
+    assert b.count().tolist() == [scan.count(tabs[o], p) for p, o in zip(preds[:12], owner[:12])]
