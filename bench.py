@@ -829,7 +829,7 @@ def typed_workload(n=60_000_000, npreds=64, sample=200_000):
     kept, cps = [], []
     for p in preds:
         try:
-            cps.append(esc.Pred(dt, types.lower(p, tmap)))
+            cps.append(esc.Pred(dt, types.lower(p, tmap, dt)))
             kept.append(p)
         except esc.EscError as e:      # an OR of several 64-bit decimal ranges may exceed the program limits
             if e.status != esc.ERR_UNSUPPORTED:

@@ -480,6 +480,46 @@ int esc_dict_range(const esc_dict *d, int op, const char *s, const char *s2, int
  * Errors: ESC_ERR_INVALID (bad literal, scale outside [0, 9]). */
 int esc_decimal_bound(const char *literal, int scale, int op, int64_t *bound, int *empty);
 
+/* Typed predicates: a predicate tree as for esc_compile_predicate whose
+ * leaves on TEXT or DECIMAL columns compare with literals (strings) instead
+ * of esc_const values; esc_lower_typed rewrites it into an ordinary tree on
+ * the int32 storage (to pass to esc_compile_predicate with the same udf
+ * program).  coltypes has one entry per schema column (NULL: all plain):
+ *  - ESC_COL_TEXT (dict): the column holds dictionary codes; leaves EQ, LT,
+ *    GT (literals[k0]), BETWEEN (literals[k0], literals[k1]), IN
+ *    (literals[k0 .. k0 + k1)) and ESC_PREFIX (strings starting with
+ *    literals[k0]), compared byte-wise;
+ *  - ESC_COL_DECIMAL (scale): the column holds value * 10^scale in int32;
+ *    leaves EQ, LT, GT, BETWEEN, IN with decimal literals
+ *    ([+-]digits[.digits], any number of digits), compared exactly;
+ *  - ESC_COL_DECIMAL64 (scale, low_col): value * 10^scale in int64 held as
+ *    two word columns: this column the high 32 bits (signed), low_col the
+ *    low 32 bits with the sign bit flipped (esc_decimal64_words); the same
+ *    leaves, lowered to tests on both columns.
+ * Leaves on plain columns and UDF leaves keep their esc_const constants.
+ * The output consts are int32 (typed leaves) or copies of the input ones.
+ * Errors: ESC_ERR_INVALID (indices, bad literal, missing dictionary),
+ * ESC_ERR_TYPE (a prefix on a non-TEXT column, a typed column not stored as
+ * int32), ESC_ERR_CAPACITY (output arrays too small: *out_nnodes and
+ * *out_nconsts give the sizes needed).  Host only. */
+typedef enum { ESC_COL_PLAIN = 0, ESC_COL_TEXT = 1, ESC_COL_DECIMAL = 2, ESC_COL_DECIMAL64 = 3 } esc_col_kind;
+enum { ESC_PREFIX = 8 };   /* typed leaf op: TEXT prefix match */
+typedef struct {
+    int32_t kind;           /* esc_col_kind */
+    int32_t scale;          /* DECIMAL, DECIMAL64: digits after the point, 0..9 */
+    int32_t low_col;        /* DECIMAL64: column of the low words */
+    int32_t pad;
+    const esc_dict *dict;   /* TEXT */
+} esc_col_type;
+int esc_lower_typed(const esc_table *schema, const esc_col_type *coltypes, const esc_node *nodes, int nnodes,
+                    const esc_const *consts, int nconsts, const char *const *literals, int nliterals,
+                    esc_node *out_nodes, int max_nodes, int *out_nnodes, esc_const *out_consts, int max_consts,
+                    int *out_nconsts);
+/* The word columns of int64 values (host arrays): high[i] = values[i] >> 32,
+ * low[i] = (low 32 bits) XOR 0x80000000 as int32, so that the order of the
+ * values is the lexicographic order of (high, low) as int32 pairs. */
+int esc_decimal64_words(const int64_t *values, int64_t n, int32_t *high, int32_t *low);
+
 /* ------------------------------------------------------------------ hash join
  *
  * Section 2.2: a left-deep plan probes the largest relation and builds hash

@@ -119,6 +119,9 @@ def lib():
             "esc_batch_create": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(BatchOpts), vp, ctypes.c_size_t, vp,
                                   P(vp)], ctypes.c_int),
             "esc_batch_tune_cache_load": ([ctypes.c_char_p, P(ctypes.c_int), P(ctypes.c_int)], ctypes.c_int),
+            "esc_lower_typed": ([vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
+                                 P(ctypes.c_int), vp, ctypes.c_int, P(ctypes.c_int)], ctypes.c_int),
+            "esc_decimal64_words": ([vp, i64, vp, vp], ctypes.c_int),
             "esc_batch_update": ([vp, vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_batch_count": ([vp, vp, vp], ctypes.c_int),
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),

@@ -4,11 +4,12 @@ Section 3 (Table 3) measures predicates on TEXT and DECIMAL(15,2) columns.
 Here a TEXT column is stored as dictionary codes (rank in the dictionary's
 byte-wise order) and a DECIMAL(p, s) column as value * 10^s in int32, or,
 when its values exceed int32, in int64 held as two 32-bit word columns
-(split_words); the library translates a string or decimal comparison into a code range or an
-exact int32 bound (esc_dict_range, esc_decimal_bound), and `lower` rewrites
-a predicate description into int32 leaves on the stored values, which the
-ordinary compiler and kernels then evaluate.  Everything here runs on the
-host; the library's dictionary and decimal routines do the comparisons.
+(split_words, by the library's esc_decimal64_words).  The library rewrites
+a predicate whose leaves compare typed columns with strings or decimal
+literals into int32 leaves on the stored values (esc_lower_typed: code
+ranges and sets, exact decimal bounds, 64-bit ranges on word columns),
+which the ordinary compiler and kernels then evaluate; this module only
+marshals the descriptions.
 
 Extra leaf forms on typed columns: ("eq"|"lt"|"gt", c, v), ("between", c,
 a, b), ("in", c, [v...]) with str constants on TEXT columns and decimal
@@ -74,151 +75,177 @@ class Dict:
             self.h = None
 
 
+def _literal(v):
+    """Text of a decimal literal given as a string or a decimal.Decimal
+    (written out in positional notation)."""
+    return format(v, "f") if isinstance(v, Decimal) else str(v)
+
+
 def decimal_bound(literal, scale, op):
     """(bound, empty) of esc_decimal_bound for a literal given as a string
-    or a decimal.Decimal (written out in positional notation)."""
-    text = format(literal, "f") if isinstance(literal, Decimal) else str(literal)
+    or a decimal.Decimal."""
     b, e = ctypes.c_int64(), ctypes.c_int()
-    esc.check(esc.lib().esc_decimal_bound(text.encode(), int(scale), op, ctypes.byref(b), ctypes.byref(e)))
+    esc.check(esc.lib().esc_decimal_bound(_literal(literal).encode(), int(scale), op, ctypes.byref(b),
+                                          ctypes.byref(e)))
     return b.value, bool(e.value)
-
-
-def _range_leaf(c, lo, hi):
-    """lo <= x <= hi on int32 column c (int64 bounds; empty -> false)."""
-    lo, hi = max(lo, I32_MIN), min(hi, I32_MAX)
-    if lo > hi:
-        return ("lt", c, I32_MIN)
-    return ("between", c, int(lo), int(hi))
-
-
-def _text_leaf(d: Dict, leaf):
-    op, c = leaf[0], leaf[1]
-    if op == "in":
-        codes = sorted({lo for lo, hi in (d.range(esc.EQ, v) for v in leaf[2]) if lo <= hi})
-        return ("in", c, codes) if codes else ("lt", c, I32_MIN)
-    if op == "prefix":
-        return _range_leaf(c, *d.range(esc.DICT_PREFIX, leaf[2]))
-    if op == "between":
-        return _range_leaf(c, *d.range(esc.BETWEEN, leaf[2], leaf[3]))
-    return _range_leaf(c, *d.range({"eq": esc.EQ, "lt": esc.LT, "gt": esc.GT}[op], leaf[2]))
-
-
-def _decimal_leaf(scale, leaf):
-    op, c = leaf[0], leaf[1]
-    if op == "in":
-        vals = sorted({v for v, e in (decimal_bound(x, scale, esc.EQ) for x in leaf[2]) if not e})
-        vals = [v for v in vals if I32_MIN <= v <= I32_MAX]
-        return ("in", c, vals) if vals else ("lt", c, I32_MIN)
-    if op == "eq":
-        v, empty = decimal_bound(leaf[2], scale, esc.EQ)
-        return ("lt", c, I32_MIN) if empty else _range_leaf(c, v, v)
-    if op == "lt":
-        return _range_leaf(c, I32_MIN, decimal_bound(leaf[2], scale, esc.LT)[0])
-    if op == "gt":
-        return _range_leaf(c, decimal_bound(leaf[2], scale, esc.GT)[0], I32_MAX)
-    if op == "between":   # a <= x <= b: above the largest value below a, below the smallest above b
-        lo = decimal_bound(leaf[2], scale, esc.LT)[0] + 1
-        hi = decimal_bound(leaf[3], scale, esc.GT)[0] - 1
-        return _range_leaf(c, lo, hi)
-    raise ValueError(f"{op} is not a decimal comparison")
 
 
 # ---------------------------------------------------------------- 64-bit decimals as two word columns
 #
 # A DECIMAL(15,2) value needs up to 10^15 stored units, beyond int32.  Such
 # a column is stored as two 4-byte columns: H = the high 32 bits (signed)
-# and L = the low 32 bits with the sign bit flipped, so that the signed
-# order of L is the unsigned order of the low word.  The order of the 64-bit
-# values is then the lexicographic order of (H, L), and every comparison
-# with a 64-bit bound becomes a few int32 leaves on H and L; the scans keep
-# their 16-byte loads and 32-bit compares and read 8 bytes per row.
+# and L = the low 32 bits with the sign bit flipped (esc_decimal64_words), so
+# that the order of the 64-bit values is the lexicographic order of (H, L);
+# the library lowers every comparison on it to int32 leaves on H and L.
 
 def split_words(x):
-    """(H, L) int32 word columns of an int64 array (numpy or torch)."""
-    if isinstance(x, np.ndarray):
-        x = x.astype(np.int64)
-        hi = (x >> 32).astype(np.int32)
-        lo = ((x & 0xFFFFFFFF) ^ 0x80000000).astype(np.uint32).view(np.int32)
-        return hi, lo
-    import torch
-    hi = (x >> 32).to(torch.int32)
-    lo = ((x & 0xFFFFFFFF) ^ 0x80000000)
-    lo = torch.where(lo >= 2**31, lo - 2**32, lo).to(torch.int32)
+    """(H, L) int32 word columns of an int64 array (numpy, or a torch tensor
+    on the host or the device, returned where it was)."""
+    torch_in = not isinstance(x, np.ndarray)
+    host = x.cpu().numpy() if torch_in else x
+    v = np.ascontiguousarray(host, np.int64)
+    hi = np.empty(v.shape, np.int32)
+    lo = np.empty(v.shape, np.int32)
+    esc.check(esc.lib().esc_decimal64_words(v.ctypes.data, v.size, hi.ctypes.data, lo.ctypes.data))
+    if torch_in:
+        import torch
+        return torch.from_numpy(hi).to(x.device), torch.from_numpy(lo).to(x.device)
     return hi, lo
 
 
-def _words(c):
-    h = c >> 32
-    lo = (c & 0xFFFFFFFF) ^ 0x80000000
-    return h, lo - 2**32 if lo >= 2**31 else lo
+# ---------------------------------------------------------------- lowering (in the library)
+
+_KIND = {"text": 1, "decimal": 2, "decimal64": 3}
+_TYPED_OPS = {"eq": esc.EQ, "lt": esc.LT, "gt": esc.GT, "between": esc.BETWEEN, "in": esc.IN, "prefix": 8}
+_NAMES = {esc.EQ: "eq", esc.LT: "lt", esc.GT: "gt", esc.BETWEEN: "between", esc.IN: "in"}
 
 
-def _range64(H, L, lo, hi):
-    """lo <= x <= hi on the 64-bit column (H, L); bounds are Python ints
-    within +-(10^18 + 1), or None for an open end."""
-    if lo is not None and hi is not None and lo > hi:
-        return ("lt", H, I32_MIN)
-    parts = []
-    lh = ll = hh = hl = None
-    if lo is not None:
-        lh, ll = _words(lo)
-    if hi is not None:
-        hh, hl = _words(hi)
-    if lo is not None and hi is not None and lh == hh:
-        return ("and", [("eq", H, lh), ("between", L, ll, hl)])
-    parts.append(("between", H, lh if lo is not None else I32_MIN, hh if hi is not None else I32_MAX))
-    if lo is not None:    # H > lh or L >= ll
-        parts.append(("or", [("gt", H, lh), ("between", L, ll, I32_MAX)]))
-    if hi is not None:    # H < hh or L <= hl
-        parts.append(("or", [("lt", H, hh), ("between", L, I32_MIN, hl)]))
-    return ("and", parts) if len(parts) > 1 else parts[0]
+class ColType(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("scale", ctypes.c_int32), ("low_col", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("dict", ctypes.c_void_p)]
 
 
-def _decimal64_leaf(scale, L, leaf):
-    op, H = leaf[0], leaf[1]
-    if op == "in":
-        vals = sorted({v for v, e in (decimal_bound(x, scale, esc.EQ) for x in leaf[2]) if not e})
-        if not vals:
-            return ("lt", H, I32_MIN)
-        groups = {}
-        for v in vals:
-            h, lo = _words(v)
-            groups.setdefault(h, []).append(lo)
-        # H in {h} and, for each h, (H != h or L in lows(h))
-        parts = [("in", H, sorted(groups))]
-        for h, lows in sorted(groups.items()):
-            if len(groups) == 1:
-                parts.append(("in", L, lows))
+def _dtypes_of(schema):
+    return list(schema.dtypes) if hasattr(schema, "dtypes") else list(schema)
+
+
+def lower(pred, types, schema):
+    """The predicate with its leaves on typed columns rewritten by the
+    library (esc_lower_typed) into int32 leaves on their storage.  types maps
+    a column to ("text", Dict), ("decimal", scale) (value * 10^scale in
+    int32) or ("decimal64", scale, L) (value * 10^scale in int64 held as the
+    word columns H = this column and L, see split_words); schema is an
+    esc.Table or the column dtypes.  Other leaves are kept."""
+    dtypes = _dtypes_of(schema)
+    nodes, consts, lits, udfs = [], [], [], []
+
+    def const(v, dt):
+        c = esc.Const()
+        c.dtype = dt
+        if dt == esc.FLOAT32:
+            c.v.bits = int(np.asarray(v, np.float32).view(np.uint32))
+        else:
+            c.v.i = int(v)
+        consts.append(c)
+        return len(consts) - 1
+
+    def lit(v, kind):
+        if kind == "text":
+            lits.append(_c_str(v))
+        else:
+            lits.append(_literal(v).encode())
+        return len(lits) - 1
+
+    def walk(p):
+        n = esc.Node()
+        nodes.append(n)
+        op = p[0]
+        if op in ("and", "or"):
+            n.op = esc.AND if op == "and" else esc.OR
+            n.nchild = len(p[1])
+            for q in p[1]:
+                walk(q)
+            return
+        if op == "udf":   # kept as it is: the library copies the node, the description is put back
+            n.op, n.cmp, n.k0 = esc.UDF, esc.EQ, const(0, esc.INT32)
+            udfs.append(p)
+            return
+        c = p[1]
+        n.col = c
+        n.op = _TYPED_OPS[op]
+        if c in types:
+            kind = types[c][0]
+            if op == "in":
+                n.k0, n.k1 = len(lits), len(p[2])
+                for v in p[2]:
+                    lit(v, kind)
+            elif op == "between":
+                n.k0, n.k1 = lit(p[2], kind), lit(p[3], kind)
             else:
-                parts.append(("or", [("lt", H, h), ("gt", H, h), ("in", L, lows)]))
-        return ("and", parts)
-    if op == "eq":
-        v, empty = decimal_bound(leaf[2], scale, esc.EQ)
-        return ("lt", H, I32_MIN) if empty else _range64(H, L, v, v)
-    if op == "lt":
-        return _range64(H, L, None, decimal_bound(leaf[2], scale, esc.LT)[0])
-    if op == "gt":
-        return _range64(H, L, decimal_bound(leaf[2], scale, esc.GT)[0], None)
-    if op == "between":
-        lo = decimal_bound(leaf[2], scale, esc.LT)[0] + 1
-        hi = decimal_bound(leaf[3], scale, esc.GT)[0] - 1
-        return _range64(H, L, lo, hi)
-    raise ValueError(f"{op} is not a decimal comparison")
+                n.k0 = lit(p[2], kind)
+            return
+        dt = dtypes[c]
+        if op == "in":
+            n.k0, n.k1 = len(consts), len(p[2])
+            for v in p[2]:
+                const(v, dt)
+        elif op == "between":
+            n.k0, n.k1 = const(p[2], dt), const(p[3], dt)
+        else:
+            n.k0 = const(p[2], dt)
+
+    walk(pred)
+    ct = (ColType * len(dtypes))()
+    for c, t in types.items():
+        ct[c].kind = _KIND[t[0]]
+        if t[0] == "text":
+            ct[c].dict = t[1].h.value
+        else:
+            ct[c].scale = int(t[1])
+            if t[0] == "decimal64":
+                ct[c].low_col = int(t[2])
+    schema_t = esc.Table(0, dtypes, None)
+    arr_n = (esc.Node * len(nodes))(*nodes)
+    arr_c = (esc.Const * max(len(consts), 1))(*consts)
+    arr_l = (ctypes.c_char_p * max(len(lits), 1))(*lits)
+    cap_n, cap_c = 64 + 8 * len(nodes), 64 + 8 * len(consts) + 4 * len(lits)
+    while True:
+        out_n = (esc.Node * cap_n)()
+        out_c = (esc.Const * cap_c)()
+        nn, nc = ctypes.c_int(), ctypes.c_int()
+        rc = esc.lib().esc_lower_typed(schema_t.h, ct, arr_n, len(nodes), arr_c, len(consts), arr_l, len(lits),
+                                       out_n, cap_n, ctypes.byref(nn), out_c, cap_c, ctypes.byref(nc))
+        if rc != esc.ERR_CAPACITY:
+            esc.check(rc)
+            break
+        cap_n, cap_c = nn.value, nc.value
+    return _unflatten(out_n[:nn.value], out_c[:nc.value], udfs)
 
 
-def lower(pred, types):
-    """Rewrites leaves on typed columns; types maps a column to ("text",
-    Dict), ("decimal", scale) (value * 10^scale in int32) or ("decimal64",
-    scale, L) (value * 10^scale in int64 as the word columns H = this
-    column and L, see split_words).  Other leaves are kept."""
-    op = pred[0]
-    if op in ("and", "or"):
-        return (op, [lower(q, types) for q in pred[1]])
-    if op == "udf" or pred[1] not in types:
-        return pred
-    kind, arg = types[pred[1]][0], types[pred[1]][1]
-    if kind == "text":
-        return _text_leaf(arg, pred)
-    if kind == "decimal64":
-        return _decimal64_leaf(arg, types[pred[1]][2], pred)
-    return _decimal_leaf(arg, pred)
+def _unflatten(nodes, consts, udfs):
+    """The description of a lowered node array (int32 and float32 constants)."""
+    pos = 0
+    it = iter(udfs)
+
+    def val(k):
+        c = consts[k]
+        if c.dtype == esc.FLOAT32:
+            return np.uint32(c.v.bits).view(np.float32)
+        return int(c.v.i)
+
+    def rec():
+        nonlocal pos
+        n = nodes[pos]
+        pos += 1
+        if n.op in (esc.AND, esc.OR):
+            return ("and" if n.op == esc.AND else "or", [rec() for _ in range(n.nchild)])
+        if n.op == esc.UDF:
+            return next(it)
+        name = _NAMES[n.op]
+        if n.op == esc.IN:
+            return (name, n.col, [val(n.k0 + i) for i in range(n.k1)])
+        if n.op == esc.BETWEEN:
+            return (name, n.col, val(n.k0), val(n.k1))
+        return (name, n.col, val(n.k0))
+
+    return rec()

@@ -53,7 +53,7 @@ def test_typed_counts_and_rows(ctx, n, seed, npreds):
     for i, p in enumerate(preds):
         want = np.flatnonzero(typed.eval_rows(raw, KINDS, p)) if n else np.zeros(0, np.int64)
         try:
-            cp = esc.Pred(dt, types.lower(p, tmap))
+            cp = esc.Pred(dt, types.lower(p, tmap, dt))
         except esc.EscError as e:     # rare ORs of several 64-bit decimal ranges exceed the program limits
             assert e.status == esc.ERR_UNSUPPORTED, (e, p)
             unsupported += 1

@@ -7,6 +7,8 @@ predicates onto the stored int32 columns is checked end to end against the
 typed oracle by counting the lowered predicates with the scan oracle."""
 from decimal import Decimal
 
+import os
+
 import numpy as np
 import pytest
 
@@ -160,10 +162,14 @@ def test_word_split_order():
 
 
 def test_range64_brute_force():
+    """Every 64-bit range between word-edge bounds (and open ends), lowered by
+    the library onto the two word columns (a DECIMAL(18,0) column, so each
+    literal is its stored value), against numpy's int64 comparison."""
     edges = sorted({e + d for e in dg.WIDE_EDGES for d in (-1, 0, 1)} | {-7 * 2**32 + 5, 3 * 2**32})
     x = np.array(edges, dtype=np.int64)
     hi, lo = types.split_words(x)
     t = dg.Table("w", len(x), [dg.INT32] * 2, [hi, lo], ["h", "l"], [None] * 2)
+    tmap = {0: ("decimal64", 0, 1)}
     bounds = edges[::2] + [None]
     for a in bounds:
         for c in bounds:
@@ -172,8 +178,36 @@ def test_range64_brute_force():
                 want &= x >= a
             if c is not None:
                 want &= x <= c
-            got = scan.eval_rows(t, types._range64(0, 1, a, c)).astype(bool)
+            if a is not None and c is not None:
+                p = ("between", 0, str(a), str(c))
+            elif a is not None:
+                p = ("gt", 0, str(a - 1))          # x > a - 1 <=> x >= a for integers
+            elif c is not None:
+                p = ("lt", 0, str(c + 1))
+            else:
+                continue
+            got = scan.eval_rows(t, types.lower(p, tmap, t.dtypes)).astype(bool)
             assert np.array_equal(got, want), (a, c)
+
+
+def test_lowering_errors_and_capacity():
+    """The library refuses a prefix match on a DECIMAL column, a typed
+    column not stored as int32 and a malformed literal, and reports the
+    sizes a too-small output needs."""
+    d = types.Dict(["a", "b"])
+    with pytest.raises(esc.EscError) as e:
+        types.lower(("prefix", 1, "1"), {0: ("text", d), 1: ("decimal", 2)}, [dg.INT32, dg.INT32])
+    assert e.value.status == esc.ERR_TYPE
+    with pytest.raises(esc.EscError) as e:
+        types.lower(("eq", 0, "1.5"), {0: ("decimal", 2)}, [dg.FLOAT32])
+    assert e.value.status == esc.ERR_TYPE
+    with pytest.raises(esc.EscError) as e:
+        types.lower(("eq", 0, "1.2.3"), {0: ("decimal", 2)}, [dg.INT32])
+    assert e.value.status == esc.ERR_INVALID
+    # an IN of many wide values grows the tree beyond the first guess of its size
+    vals = [str(v) for v in range(0, 2**32 * 40, 2**32 + 7)]
+    low = types.lower(("in", 0, vals), {0: ("decimal64", 0, 1)}, [dg.INT32, dg.INT32])
+    assert low[0] == "and" and len(low[1]) == 1 + len(vals)
 
 
 def typed_workload(n, seed):
@@ -203,7 +237,7 @@ def test_lowered_counts_match_typed_oracle():
     nonzero = 0
     for p in preds:
         want = typed.eval_rows(raw, kinds, p)
-        got = scan.eval_rows(t, types.lower(p, tmap))
+        got = scan.eval_rows(t, types.lower(p, tmap, t.dtypes))
         assert np.array_equal(got.astype(bool), want), p
         nonzero += 0 < want.sum() < len(want)
     assert nonzero > 40      # the workload is not degenerate
@@ -221,7 +255,7 @@ def test_lowered_predicates_compile():
     preds = dg.typed_preds(vocab, np.random.default_rng(23), 400, wide=wide[:1000])
     for p in preds:
         try:
-            esc.Pred(st, types.lower(p, tmap))
+            esc.Pred(st, types.lower(p, tmap, t.dtypes))
         except esc.EscError as e:
             assert e.status == esc.ERR_UNSUPPORTED, (e, p)
             unsupported += 1
@@ -251,5 +285,20 @@ def test_lowering_edge_cases():
     ]
     for p in cases:
         want = typed.eval_rows(raw, kinds, p)
-        got = scan.eval_rows(t, types.lower(p, tmap)).astype(bool)
+        got = scan.eval_rows(t, types.lower(p, tmap, t.dtypes)).astype(bool)
         assert np.array_equal(got, want), p
+
+
+def test_c_caller_lowers_a_wide_decimal_predicate(tmp_path):
+    """tests/c/lower_typed.c, built with gcc against include/esc.h and the
+    built libesc.so, lowers and compiles a 64-bit DECIMAL range and a TEXT
+    prefix through the C ABI alone."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib_dir = os.path.dirname(esc.LIB_PATH)
+    exe = tmp_path / "lower_typed"
+    subprocess.run(["gcc", "-std=c11", "-O1", "-Wall", "-I", os.path.join(root, "include"),
+                    os.path.join(root, "tests", "c", "lower_typed.c"), "-o", str(exe), "-L", lib_dir, "-lesc",
+                    "-Wl,-rpath," + lib_dir], check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
