@@ -371,6 +371,14 @@ int esc_batch_destroy(esc_batch *b);
 int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
                   const esc_value *col_sample, int sample_size, const esc_pred *const *preds, int npreds,
                   float *host_out);
+/* The same featurization with the catalog's column CDFs built once
+ * (esc_catalog_create takes the arguments esc_featurize takes for the
+ * catalog, with the same errors); the features are identical bit for bit. */
+typedef struct esc_catalog esc_catalog;
+int esc_catalog_create(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
+                       const esc_value *col_sample, int sample_size, esc_catalog **out);
+int esc_catalog_destroy(esc_catalog *cat);
+int esc_featurize_catalog(const esc_catalog *cat, const esc_pred *const *preds, int npreds, float *host_out);
 
 /* MLP 64 -> 256 -> 256 -> 256 -> 1 (ReLU) predicting ln(selectivity).
  * bfloat16 MFMA operands, float32 accumulation, float32 master weights and

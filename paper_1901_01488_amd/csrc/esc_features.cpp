@@ -280,36 +280,74 @@ double log_sel(float yhat, int64_t n)
 
 extern "C" {
 
-int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
-                  const esc_value *col_sample, int sample_size, const esc_pred *const *preds, int npreds,
-                  float *host_out)
-{
-    if (!schema || !col_min || !col_max || (npreds > 0 && (!preds || !host_out)) || npreds < 0)
-        return fail(ESC_ERR_INVALID, "null argument");
-    if (sample_size < 0 || (sample_size > 0 && !col_sample)) return fail(ESC_ERR_INVALID, "bad column sample");
-    const int ncols = (int)schema->dtypes.size();
-    const int nc = std::min(ncols, kNCF);
+}  // extern "C"
+
+// The column CDFs of a table's catalog, built once and reused by every
+// featurization (building them sorts each column's sample).
+struct esc_catalog {
+    std::vector<int32_t> dtypes;
     Cdf cdf[kNCF];
+};
+
+extern "C" {
+
+int esc_catalog_create(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
+                       const esc_value *col_sample, int sample_size, esc_catalog **out)
+{
+    if (!schema || !col_min || !col_max || !out) return fail(ESC_ERR_INVALID, "null argument");
+    if (sample_size < 0 || (sample_size > 0 && !col_sample)) return fail(ESC_ERR_INVALID, "bad column sample");
+    esc_catalog *cat = new esc_catalog;
+    cat->dtypes = schema->dtypes;
+    const int nc = std::min((int)schema->dtypes.size(), kNCF);
     for (int c = 0; c < nc; c++) {
         const bool fl = schema->dtypes[c] == ESC_FLOAT32;
         auto val = [&](esc_value v) { return fl ? (double)v.f : (double)v.i; };
         std::vector<double> smp((size_t)sample_size);
         for (int i = 0; i < sample_size; i++) smp[i] = val(col_sample[(size_t)c * sample_size + i]);
         const double lo = val(col_min[c]), hi = val(col_max[c]);
-        if (isnan(lo) || isnan(hi) || lo > hi)
+        if (isnan(lo) || isnan(hi) || lo > hi) {
+            delete cat;
             return fail(ESC_ERR_INVALID, "column %d: catalog minimum / maximum not ordered", c);
-        cdf[c].build(smp, lo, hi, !fl);
+        }
+        cat->cdf[c].build(smp, lo, hi, !fl);
     }
+    *out = cat;
+    return ESC_OK;
+}
+
+int esc_catalog_destroy(esc_catalog *cat)
+{
+    delete cat;
+    return ESC_OK;
+}
+
+int esc_featurize_catalog(const esc_catalog *cat, const esc_pred *const *preds, int npreds, float *host_out)
+{
+    if (!cat || (npreds > 0 && (!preds || !host_out)) || npreds < 0) return fail(ESC_ERR_INVALID, "null argument");
     double f[kNF];
     for (int i = 0; i < npreds; i++) {
         if (!preds[i]) return fail(ESC_ERR_INVALID, "predicate %d is null", i);
-        if (preds[i]->schema_dtypes != schema->dtypes)
+        if (preds[i]->schema_dtypes != cat->dtypes)
             return fail(ESC_ERR_INVALID, "predicate %d was compiled for another schema", i);
-        Walk W{preds[i], cdf, f};
+        Walk W{preds[i], cat->cdf, f};
         featurize_one(W);
         for (int k = 0; k < kNF; k++) host_out[(size_t)i * kNF + k] = (float)f[k];
     }
     return ESC_OK;
+}
+
+int esc_featurize(const esc_table *schema, const esc_value *col_min, const esc_value *col_max,
+                  const esc_value *col_sample, int sample_size, const esc_pred *const *preds, int npreds,
+                  float *host_out)
+{
+    if (!schema || !col_min || !col_max || (npreds > 0 && (!preds || !host_out)) || npreds < 0)
+        return fail(ESC_ERR_INVALID, "null argument");
+    esc_catalog *cat = nullptr;
+    int rc = esc_catalog_create(schema, col_min, col_max, col_sample, sample_size, &cat);
+    if (rc) return rc;
+    rc = esc_featurize_catalog(cat, preds, npreds, host_out);
+    esc_catalog_destroy(cat);
+    return rc;
 }
 
 int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau, double beta, int64_t min_rows,

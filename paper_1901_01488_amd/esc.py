@@ -127,6 +127,9 @@ def lib():
             "esc_batch_get_opts": ([vp, P(BatchOpts)], ctypes.c_int),
             "esc_batch_destroy": ([vp], ctypes.c_int),
             "esc_featurize": ([vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_int, vp], ctypes.c_int),
+            "esc_catalog_create": ([vp, vp, vp, vp, ctypes.c_int, P(vp)], ctypes.c_int),
+            "esc_catalog_destroy": ([vp], ctypes.c_int),
+            "esc_featurize_catalog": ([vp, vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_mlp_state_bytes": ([], ctypes.c_size_t),
             "esc_mlp_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
             "esc_mlp_create": ([vp, vp, ctypes.c_size_t, P(vp)], ctypes.c_int),
@@ -512,10 +515,7 @@ class Batch:
 
 # ------------------------------------------------------------------ learned gate
 
-def featurize(schema: Table, preds, cmin, cmax, sample=None):
-    """64 float32 features per compiled predicate (host, in the library).
-    sample: per column c < min(ncols, 6), the same number of row values (or
-    None: no sample)."""
+def _catalog_args(schema: Table, cmin, cmax, sample):
     nc = min(len(schema.dtypes), 6)
     vmin = (Value * len(schema.dtypes))()
     vmax = (Value * len(schema.dtypes))()
@@ -540,10 +540,39 @@ def featurize(schema: Table, preds, cmin, cmax, sample=None):
         else:
             bits = col.astype(np.int64).astype(np.int32).view(np.uint32)
         ctypes.memmove(ctypes.addressof(vs) + c * m * 4, bits.ctypes.data, m * 4)
+    return vmin, vmax, vs, m
+
+
+def featurize(schema: Table, preds, cmin, cmax, sample=None):
+    """64 float32 features per compiled predicate (host, in the library).
+    sample: per column c < min(ncols, 6), the same number of row values (or
+    None: no sample)."""
+    vmin, vmax, vs, m = _catalog_args(schema, cmin, cmax, sample)
     ph = (ctypes.c_void_p * max(len(preds), 1))(*[p.h for p in preds])
     out = np.zeros((len(preds), 64), np.float32)
     check(lib().esc_featurize(schema.h, vmin, vmax, vs, m, ph, len(preds), out.ctypes.data))
     return out
+
+
+class Catalog:
+    """A table's catalog in the library (column CDFs built once)."""
+
+    def __init__(self, schema: Table, cmin, cmax, sample=None):
+        vmin, vmax, vs, m = _catalog_args(schema, cmin, cmax, sample)
+        h = ctypes.c_void_p()
+        check(lib().esc_catalog_create(schema.h, vmin, vmax, vs, m, ctypes.byref(h)))
+        self.h = h
+
+    def featurize(self, preds):
+        ph = (ctypes.c_void_p * max(len(preds), 1))(*[p.h for p in preds])
+        out = np.zeros((len(preds), 64), np.float32)
+        check(lib().esc_featurize_catalog(self.h, ph, len(preds), out.ctypes.data))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.esc_catalog_destroy(self.h)
+            self.h = None
 
 
 def params_to_flat(params):

@@ -89,8 +89,10 @@ class Estimator:
         self.nrows = schema.nrows
 
     def features(self, preds):
-        c = self.catalog
-        return esc.featurize(self.schema, preds, c.cmin, c.cmax, c.sample)
+        if getattr(self, "_lib_catalog", None) is None:
+            c = self.catalog
+            self._lib_catalog = esc.Catalog(self.schema, c.cmin, c.cmax, c.sample)
+        return self._lib_catalog.featurize(preds)
 
     def train(self, x, y, epochs, batch, lr, order_seed):
         import torch

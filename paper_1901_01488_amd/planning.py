@@ -11,8 +11,10 @@ all but the largest relation).  The optimizer needs, per query:
   - join order: the smaller filtered build relation first (Section 2.2);
   - no push-down on the probe relation (Section 2.2), so its cardinality
     does not change the plan.
-Latency of a query is the time from its arrival until its three
-selectivities are decided.
+Every mode takes `exact_probe`: with it off, no mode counts the probe
+relation's selection (the plan does not depend on it); with it on, every
+mode counts it.  Modes are thus compared on identical work.  Latency of a
+query is the time from its arrival until its selectivities are decided.
 """
 from __future__ import annotations
 
@@ -54,8 +56,9 @@ class Workload:
         self.batch = None   # one batched handle, re-planned per micro-batch
 
     # --------------------------------------------------------- plain
-    def run_plain(self):
-        """Queries in arrival order; each selectivity by one esc_count."""
+    def run_plain(self, exact_probe=True):
+        """Queries in arrival order; each needed selectivity by one esc_count."""
+        tabs = range(3) if exact_probe else range(2)
         n = len(self.queries)
         done = np.zeros(n)
         counts = np.zeros((n, 3), np.uint64)
@@ -64,17 +67,22 @@ class Workload:
             now = time.perf_counter() - t0
             if now < self.arrivals[i]:
                 time.sleep(self.arrivals[i] - now)
-            for t in range(3):
+            for t in tabs:
                 counts[i, t] = self.ctx.count(self.tables[t], self.cps[i][t], ws=self.ws[t])
             done[i] = time.perf_counter() - t0
         return self._report(done, counts, 3 * n, "plain")
 
     # --------------------------------------------------------- batched (+ gate)
-    def run_batched(self, window=64, max_wait_s=1e-3, gate=None, estimators=None, gcfg: GateConfig = None):
+    def run_batched(self, window=64, max_wait_s=1e-3, gate=None, estimators=None, gcfg: GateConfig = None,
+                    exact_probe=True):
         """Micro-batches of arriving queries: when `window` queries are
         pending or the oldest has waited max_wait_s, the pending selections
         go to one batched graph launch.  With a gate, each pending selection
-        is first estimated and only the routed ones are counted exactly."""
+        is first estimated and only the routed ones are counted exactly (the
+        gate's exact_probe decides for the probe relation)."""
+        if gcfg is not None:
+            exact_probe = gcfg.exact_probe
+        ntabs = 3 if exact_probe else 2
         n = len(self.queries)
         done = np.zeros(n)
         counts = np.zeros((n, 3), np.uint64)
@@ -109,20 +117,18 @@ class Workload:
                     now = time.perf_counter() - t0
                     while j < n and j - i < window and self.arrivals[j] <= now:
                         j += 1
-            sel = [(q, t) for q in range(i, j) for t in range(3)]
-            need = sel
+            need = [(q, t) for q in range(i, j) for t in range(ntabs)]
             if gate is not None:
                 need = []
-                for t in range(3):
-                    qs = [q for q in range(i, j)]
-                    x = estimators[t].features([self.cps[q][t] for q in qs])
+                # the build relations' selections are estimated; no plan
+                # decision reads the probe relation's (it is counted or not
+                # according to exact_probe, as in the other modes)
+                for t in range(2):
+                    x = estimators[t].features([self.cps[q][t] for q in range(i, j)])
                     yh = estimators[t].predict(x)
                     est[i:j, t] = yh
-                    if t < 2:
-                        r = esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows)
-                        routed[i:j, t] |= r
-                    elif gcfg.exact_probe:
-                        routed[i:j, t] = True
+                    routed[i:j, t] |= esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows)
+                routed[i:j, 2] = gcfg.exact_probe
                 for q in range(i, j):
                     if esc.gate_join_pair(est[q, 0], nrows[0], est[q, 1], nrows[1], gcfg.beta):
                         routed[q, 0] = routed[q, 1] = True
@@ -131,7 +137,8 @@ class Workload:
                 preds = [self.cps[q][t] for q, t in need]
                 owners = [t for _, t in need]
                 if self.batch is None:
-                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16)
+                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16,
+                                           max_preds=3 * window)
                 else:
                     self.batch.update(preds, owners)
                 c = self.batch.count()

@@ -65,3 +65,15 @@ def test_gate_matches_oracle():
         assert esc.gate_join_pair(yr, nr, ys, ns, 1.5) == fo.route_join_pair(yr, nr, ys, ns, 1.5)
     # a prediction exactly at tau is routed
     assert esc.gate_pushdown(np.array([math.log(0.05)], np.float32), 10**8, 0.05, 1.25, 10**6)[0]
+
+
+def test_catalog_handle_matches_featurize():
+    """Features from a catalog built once equal esc_featurize's bit for bit."""
+    from paper_1901_01488_amd import learned
+    t = dg.tables_planning([50_000])[0]
+    st = esc.Table(t.nrows, t.dtypes, None)
+    cps = [esc.Pred(st, p) for p in dg.preds_mixed(t, 300, seed=3, min_conj=2, max_conj=6)]
+    cat = learned.Catalog.of(t, seed=2)
+    a = esc.featurize(st, cps, cat.cmin, cat.cmax, cat.sample)
+    b = esc.Catalog(st, cat.cmin, cat.cmax, cat.sample).featurize(cps)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
