@@ -126,6 +126,20 @@ def oracle_counts(host, specs, idx, what):
         shutil.rmtree(d, ignore_errors=True)
 
 
+def cpu_baseline_parallel(t_host, preds, counts):
+    """The oracle on P cores: the 32 predicates over all rows, one
+    single-threaded oracle per worker process (P = the host's cores, at most
+    16), scaled to GB/s of algorithmic bytes; its counts are checked against
+    the library's."""
+    idx = list(range(len(preds)))
+    got, workers, sec = oracle_counts(t_host, preds, idx, "multicore baseline")
+    nbytes = sum(len(pred_columns(p)) * t_host.nrows * 4 for p in preds)
+    return {"value": round(nbytes / sec / 1e9, 3), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "sample": f"count(*) of all {len(preds)} predicates over all {t_host.nrows} rows, one process per "
+                      f"core ({workers}), {sec:.1f} s including worker start",
+            "count_errors": int(sum(int(counts[i]) != got[i] for i in idx))}
+
+
 def cpu_baseline(t_host, preds, budget_s=25.0):
     """The oracle (single thread) on the first rows of the same table, all 32
     predicates, count only; scaled to GB/s of algorithmic bytes."""
@@ -155,6 +169,7 @@ def main():
     ap.add_argument("--rows", type=int, default=60_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the bounded learned-gate and planning extras")
     ap.add_argument("--learned", action="store_true", help="learned-gate workload (100M x 6, 200K labels)")
     ap.add_argument("--planning", action="store_true", help="planning workload (1,000 three-table queries)")
     ap.add_argument("--copy-ref", action="store_true", help="1 GiB device copy (counter calibration)")
@@ -297,6 +312,20 @@ def main():
                 extras[name + "_error"] = repr(e)[:300]
             torch.cuda.empty_cache()
 
+    if not args.no_extras and not args.no_learned:
+        # the learned gate and the planning load, bounded (the full runs are
+        # --learned and --planning): full-size estimator, fewer oracle checks;
+        # planning estimators trained on fewer labels, capacity runs only
+        for name, fn in (("learned", lambda: learned_leg(ctx, 200_000, oracle_random=100, oracle_routed=100)),
+                         ("planning", lambda: planning_leg(ctx, 1000, train_n=(20_000, 20_000, 4_000), epochs=20,
+                                                           offered=False, oracle_rs=32, oracle_p=0))):
+            try:
+                log(f"extra: {name}")
+                extras[name] = fn()
+            except Exception as e:
+                extras[name + "_error"] = repr(e)[:300]
+            torch.cuda.empty_cache()
+
     line = {
         "metric": "ESC scan GB/s vs HBM peak; predicates/s batched vs plain; p50/p99 ms/query",
         "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -308,7 +337,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(t, preds)
+        host = t.host()
+        line["cpu_baseline"] = cpu_baseline(host, preds)
+        log("cpu baseline, one process per core")
+        line["cpu_baseline_multicore"] = cpu_baseline_parallel(host, preds, counts)
     line["extras"] = extras
     print(json.dumps(line), flush=True)
 
@@ -459,23 +491,33 @@ def copy_reference():
 
 
 def learned_workload(args):
+    """Learned gate at full size: labels, training, q-error and the oracle's
+    check of 1,000 random labels and every routed test predicate."""
+    import torch
+    torch.cuda.init()
+    from paper_1901_01488_amd import esc
+    ctx = esc.Context(0)
+    r = learned_leg(ctx, args.train_preds, oracle_random=1000, oracle_routed=None)
+    print(json.dumps(r), flush=True)
+
+
+def learned_leg(ctx, ntrain, oracle_random, oracle_routed):
     """Learned gate on a 100M x 6 correlated / skewed table: exact labels by
-    the batched scan, GPU training, q-error on held-out batches of 4,096,
+    the batched scan, GPU training, q-error on a held-out batch of 4,096,
     routing and exact fallback.  Predicates are conjunctions built around
-    sampled rows (every one selects at least one row)."""
+    sampled rows (every one selects at least one row).  Routed predicates are
+    counted again by the plain count kernel (all of them) and by the oracle
+    (oracle_routed of them, None = all), beside oracle_random random labels."""
     import torch
     from paper_1901_01488_amd import datagen as dg
     from paper_1901_01488_amd import esc, learned
-    from oracle import scan
-    torch.cuda.init()
     dev = "cuda:0"
-    ctx = esc.Context(0)
     n = 100_000_000
     log("learned: table")
     t = dg.table_learned(n, device=dev)
     dt = esc.Table(t.nrows, t.dtypes, t.cols)
     catalog = learned.Catalog.of(t, seed=dg.pred_seed(3) + 1)
-    ntrain, nval, ntest = args.train_preds, 8192, 4096
+    nval, ntest = 8192, 4096
     log("learned: predicates")
     t0 = time.perf_counter()
     specs = dg.preds_anchored(t, ntrain + nval + ntest, seed=dg.pred_seed(3))
@@ -488,11 +530,14 @@ def learned_workload(args):
     label_s = time.perf_counter() - t0
     log("learned: features + training")
     est = learned.Estimator(ctx, dt, catalog, dg.mlp_init(dg.MLP_SEED))
+    t0 = time.perf_counter()
     x = est.features(cps)
+    feat_s = time.perf_counter() - t0
     y = learned.labels(counts, n)
     tr, va, te = slice(0, ntrain), slice(ntrain, ntrain + nval), slice(ntrain + nval, None)
     phases = [(20, 1e-3), (10, 2e-4), (10, 4e-5)]
     loss, train_s = est.fit(x[tr], y[tr], phases, batch=256, order_seed=dg.MLP_SEED)
+    steps = sum(e for e, _ in phases) * (ntrain // 256)
     beta = learned.validation_beta(est.predict(x[va]), counts[va], n)
     xt = torch.from_numpy(x[te]).to(dev)
     out = torch.empty(ntest, dtype=torch.float32, device=dev)
@@ -510,48 +555,65 @@ def learned_workload(args):
     q = learned.q_error(learned.c_hat(yhat, n), counts[te], n)
     route = esc.gate_pushdown(yhat, n, 0.05, beta, 1_000_000)
     idx = np.flatnonzero(route) + te.start
-    exact = learned.exact_counts(ctx, dt, [cps[i] for i in idx]) if len(idx) else np.zeros(0, np.uint64)
-    host = t.host()
+    # the routed predicates' exact fallback: the batched labels against the
+    # plain count kernel, one esc_count each
+    ws = ctx.workspace(dt, False, key="learned-count")
+    plain = np.array([ctx.count(dt, cps[i], ws=ws) for i in idx], np.uint64)
     rng = np.random.default_rng(0)
-    check = sorted(set(int(i) for i in rng.choice(len(counts), 1000, replace=False)) | set(int(i) for i in idx))
-    got, workers, oracle_s = oracle_counts(host, specs, check, "learned")
+    pick = idx if oracle_routed is None or len(idx) <= oracle_routed else rng.choice(idx, oracle_routed, replace=False)
+    check = sorted(set(int(i) for i in rng.choice(len(counts), oracle_random, replace=False)) |
+                   set(int(i) for i in pick))
+    got, workers, oracle_s = oracle_counts(t.host(), specs, check, "learned")
     oracle_errors = sum(int(counts[i]) != got[i] for i in check)
     flops = 4096 * 2 * (64 * 256 + 2 * 256 * 256 + 256)
-    print(json.dumps({
+    return {
         "workload": "learned gate: 100M x 6 table, %d training predicates, held-out batch of 4096" % ntrain,
         "label_s": round(label_s, 2), "label_row_predicates_per_s": round(len(cps) * n / label_s, 1),
-        "train_s": round(train_s, 2), "schedule": "batch 256; epochs@lr " + ", ".join(f"{e}@{l:g}" for e, l in phases),
+        "features_us_per_predicate": round(feat_s / len(cps) * 1e6, 2),
+        "train_s": round(train_s, 2), "train_steps": steps, "train_us_per_step": round(train_s / steps * 1e6, 1),
+        "schedule": "batch 256; epochs@lr " + ", ".join(f"{e}@{l:g}" for e, l in phases),
         "final_loss": float(np.mean(loss[-50:])), "zero_count_fraction": float((counts == 0).mean()),
         "inference_us_per_4096": round(infer_us, 1), "inference_tflops": round(flops / (infer_us * 1e-6) / 1e12, 3),
         "qerror_median": float(np.median(q)), "qerror_p90": float(np.quantile(q, 0.9)),
         "qerror_p99": float(np.quantile(q, 0.99)), "qerror_max": float(q.max()), "beta": beta,
-        "routed_fraction": float(route.mean()), "routed_count_errors": int((exact != counts[idx]).sum()),
+        "routed_fraction": float(route.mean()),
+        "routed_count_errors": int((plain != counts[idx]).sum()) + sum(int(counts[i]) != got[i] for i in pick),
         "cpu_baseline": {"value": round(len(check) * n / oracle_s, 1), "unit": "row-predicates/s",
                          "cores": workers, "kind": "oracle",
-                         "sample": "1000 random labels + every routed test predicate, one process per core",
+                         "sample": f"{oracle_random} random labels + {len(pick)} of the {len(idx)} routed test "
+                                   "predicates, one process per core",
                          "checked": len(check), "errors": oracle_errors, "seconds": round(oracle_s, 1)},
-        "predicate_gen_s": round(gen_s, 1)}),
-        flush=True)
+        "predicate_gen_s": round(gen_s, 1)}
 
 
 def planning_workload(args):
-    """1,000 arriving three-table queries (10M / 100M / 1B rows): plain
-    per-selection counts vs micro-batched graph launches vs batched + gate."""
+    """Planning load at full size: offered load and capacity, both probe
+    settings, the oracle on every selection of R and S and 48 on P."""
+    import torch
+    torch.cuda.init()
+    from paper_1901_01488_amd import esc
+    ctx = esc.Context(0)
+    r = planning_leg(ctx, args.queries, train_n=(100_000, 100_000, 20_000), epochs=20, offered=True,
+                     oracle_rs=None, oracle_p=48)
+    print(json.dumps(r), flush=True)
+
+
+def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
+    """nq arriving three-table queries (10M / 100M / 1B rows): plain
+    per-selection counts vs micro-batched graph launches vs batched + gate,
+    every mode on the same work.  oracle_rs: selections of R and S the oracle
+    checks (None = all); oracle_p: selections of P it checks."""
     import torch
     from paper_1901_01488_amd import datagen as dg
     from paper_1901_01488_amd import esc, learned, planning
-    torch.cuda.init()
     dev = "cuda:0"
-    ctx = esc.Context(0)
     log("planning: tables")
     tabs = dg.tables_planning(device=dev)
     dts = [esc.Table(t.nrows, t.dtypes, t.cols) for t in tabs]
-    nq = args.queries
     qs = [dg.preds_mixed(t, nq, seed=dg.pred_seed(4) + i, min_conj=2, max_conj=6) for i, t in enumerate(tabs)]
     queries = list(zip(*qs))
     arrivals = dg.poisson_arrivals(nq, 2000.0, seed=dg.pred_seed(4))
     ests = []
-    train_n = [100_000, 100_000, 20_000]
     t0 = time.perf_counter()
     for i, (t, dt) in enumerate(zip(tabs, dts)):
         log(f"planning: estimator {i}")
@@ -560,45 +622,44 @@ def planning_workload(args):
         cnt = learned.exact_counts(ctx, dt, cps)
         e = learned.Estimator(ctx, dt, learned.Catalog.of(t, seed=11 + i), dg.mlp_init(dg.MLP_SEED))
         x = e.features(cps)
-        e.train(x, learned.labels(cnt, t.nrows), epochs=20, batch=1024, lr=1e-3, order_seed=11 + i)
+        e.train(x, learned.labels(cnt, t.nrows), epochs=epochs, batch=1024, lr=1e-3, order_seed=11 + i)
         ests.append(e)
     offline_s = time.perf_counter() - t0
     # every mode does identical work: the probe relation's selection is
     # counted by no mode (exact_probe 0: no plan depends on it) or by all (1)
-    w = planning.Workload(ctx, dts, queries, arrivals)
     modes = {}
-    for probe in (0, 1):
-        log(f"planning: offered load, exact_probe {probe}")
-        gc = planning.GateConfig(beta=1.5, exact_probe=bool(probe))
-        modes[("offered", probe)] = (w.run_plain(exact_probe=bool(probe)), w.run_batched(exact_probe=bool(probe)),
-                                     w.run_batched(gate=True, estimators=ests, gcfg=gc))
-    # capacity: the same queries offered 50x faster (100,000/s), so every mode
-    # is saturated and predicates/s measures what it can sustain
-    ws = planning.Workload(ctx, dts, queries, arrivals / 50.0)
-    for probe in (0, 1):
-        log(f"planning: saturated arrivals, exact_probe {probe}")
-        gc = planning.GateConfig(beta=1.5, exact_probe=bool(probe))
-        modes[("capacity", probe)] = (ws.run_plain(exact_probe=bool(probe)), ws.run_batched(exact_probe=bool(probe)),
-                                      ws.run_batched(gate=True, estimators=ests, gcfg=gc))
-    plain, batched, gated = modes[("offered", 1)]
-    gcfg = planning.GateConfig(beta=1.5)
+    kinds = [("offered", 1.0), ("capacity", 50.0)] if offered else [("capacity", 50.0)]
+    for kind, speed in kinds:
+        w = planning.Workload(ctx, dts, queries, arrivals / speed)
+        for probe in (0, 1):
+            log(f"planning: {kind}, exact_probe {probe}")
+            gc = planning.GateConfig(beta=1.5, exact_probe=bool(probe))
+            modes[(kind, probe)] = (w.run_plain(exact_probe=bool(probe)), w.run_batched(exact_probe=bool(probe)),
+                                    w.run_batched(gate=True, estimators=ests, gcfg=gc))
+    plain = modes[(kinds[0][0], 1)][0]   # counts of all three selections
     count_errors = 0
     for (kind, probe), (pl, ba, ga) in modes.items():
         cols = [0, 1, 2] if probe else [0, 1]
         count_errors += int((pl["counts"][:, cols] != plain["counts"][:, cols]).sum())
         count_errors += int((ba["counts"][:, cols] != plain["counts"][:, cols]).sum())
         count_errors += int((ga["counts"][ga["routed"]] != plain["counts"][ga["routed"]]).sum())
-    gated = modes[("offered", 0)][2]
+    gcfg = planning.GateConfig(beta=1.5)
+    gated = modes[(kinds[0][0], 0)][2]
     r = gated["routed"]
-    exact_sel = plain["counts"] / np.array([t.nrows for t in tabs], np.float64)
-    est_sel = np.where(r, gated["counts"] / np.array([t.nrows for t in tabs], np.float64), np.exp(gated["est"]))
-    agree = np.mean([a == b for a, b in zip(planning.plans(exact_sel, [t.nrows for t in tabs], gcfg),
-                                            planning.plans(est_sel, [t.nrows for t in tabs], gcfg))])
-    # the oracle checks the exact counts: every selection on R and S, a
-    # seeded sample of 48 on the 1B-row P
-    oracle_errors, oracle_checked, oracle_rows, oracle_s = 0, 0, 0, 0.0
+    nrows = [t.nrows for t in tabs]
+    exact_sel = plain["counts"] / np.array(nrows, np.float64)
+    est_sel = np.where(r, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
+    agree = np.mean([a == b for a, b in zip(planning.plans(exact_sel, nrows, gcfg),
+                                            planning.plans(est_sel, nrows, gcfg))])
+    # the oracle checks exact counts of R and S (all, or a seeded sample) and
+    # a seeded sample of P
+    oracle_errors, oracle_checked, oracle_rows, oracle_s, workers = 0, 0, 0, 0.0, 1
+    rng = np.random.default_rng(5)
     for ti, tab in enumerate(tabs):
-        idx = list(range(nq)) if ti < 2 else sorted(np.random.default_rng(5).choice(nq, 48, replace=False).tolist())
+        want = oracle_p if ti == 2 else oracle_rs
+        if want == 0:
+            continue
+        idx = list(range(nq)) if want is None else sorted(rng.choice(nq, min(want, nq), replace=False).tolist())
         log(f"planning: oracle on table {ti} ({len(idx)} selections)")
         got, workers, sec = oracle_counts(tab.host(), [q[ti] for q in queries], idx, f"planning table {ti}")
         oracle_errors += sum(int(plain["counts"][i, ti]) != got[i] for i in idx)
@@ -614,19 +675,20 @@ def planning_workload(args):
             "batched_speedup_vs_plain": round(ba["predicates_per_s"] / pl["predicates_per_s"], 2),
             "gate_speedup_vs_plain": round(ga["predicates_per_s"] / pl["predicates_per_s"], 2),
             "gate_speedup_vs_batched": round(ga["predicates_per_s"] / ba["predicates_per_s"], 2)}
-    print(json.dumps({
-        "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s",
+    return {
+        "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s; "
+                    f"estimators trained on {'/'.join(str(v) for v in train_n)} labels, {epochs} epochs",
         "note": "every mode does the same work: exact_probe0 = no mode counts the probe relation's selection "
                 "(no plan depends on it), exact_probe1 = every mode counts it; capacity = the same queries "
-                "offered at 100,000/s; predicates/s counts all three selections of every query",
+                "offered 50x faster; predicates/s counts all three selections of every query",
         "modes": table,
         "count_errors": count_errors,
         "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1),
-        "cpu_baseline": {"value": round(oracle_rows / oracle_s, 1), "unit": "row-predicates/s", "cores": workers,
-                         "kind": "oracle", "sample": "every selection on the 10M and 100M tables, 48 seeded ones "
-                                                     "on the 1B table, one process per core",
-                         "checked": oracle_checked, "errors": oracle_errors, "seconds": round(oracle_s, 1)}}),
-        flush=True)
+        "cpu_baseline": {"value": round(oracle_rows / max(oracle_s, 1e-9), 1), "unit": "row-predicates/s",
+                         "cores": workers, "kind": "oracle",
+                         "sample": f"{'every' if oracle_rs is None else oracle_rs} selection(s) on the 10M and 100M "
+                                   f"tables, {oracle_p} on the 1B table, one process per core",
+                         "checked": oracle_checked, "errors": oracle_errors, "seconds": round(oracle_s, 1)}}
 
 
 def policy_workload():
