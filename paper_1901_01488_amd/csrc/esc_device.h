@@ -39,10 +39,12 @@ __device__ __forceinline__ void for_slot(int s, F &&f)
 template <int RPT, typename T>
 __device__ __forceinline__ uint32_t bits_of(T &&test)
 {
-    static_assert(RPT <= 32, "masks are 32-bit");
+    static_assert(RPT <= 32 && RPT % 2 == 0, "masks are 32-bit, rows come in pairs");
+    // each row selects its own bit (one select per row), two rows are merged
+    // into the mask by one three-input OR
     uint32_t m = 0;
 #pragma unroll
-    for (int r = RPT - 1; r >= 0; r--) m = m + m + (test(r) ? 1u : 0u);
+    for (int r = 0; r < RPT; r += 2) m |= (test(r) ? 1u << r : 0u) | (test(r + 1) ? 1u << (r + 1) : 0u);
     return m;
 }
 
