@@ -256,6 +256,31 @@ def main():
     value = step_bytes / (el / args.steps) / 1e9
     assert dmat.cpu().tolist() == counts
 
+    # a cold materialization of every predicate (no count before it): the
+    # single-pass compaction against count + scan + write, event-timed
+    # back to back on the stream
+    log("cold materialization")
+    cold = {}
+    os.environ["ESC_COLD_COMPACT"] = "1"
+    ctx1 = esc.Context(0)
+    del os.environ["ESC_COLD_COMPACT"]
+    wsc = torch.zeros(ws.numel(), dtype=torch.uint8, device=dev)
+    for name, cx in (("single_pass", ctx1), ("three_pass", ctx)):
+        times = []
+        for rep in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            esc.check(esc.lib().esc_workspace_init(cx.h, esc.ctypes.c_void_p(wsc.data_ptr()), wsc.numel(), None))
+            e0.record(stream)
+            for i, p in enumerate(cps):
+                # every call is cold: the previous predicate's tiles are not this one's
+                cx.materialize_async(dt, p, proj, rowids, outs, cap, dmat[i:i + 1], wsc, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+            assert dmat.cpu().tolist() == counts
+        cold[f"cold_materialize_32_{name}_ms"] = round(float(np.median(times)), 3)
+    del ctx1, wsc
+
     # dominant kernel: the count scan, timed with HIP events on the stream it
     # runs on.  The 32 predicates' launches run back to back between two
     # events after a 1 GiB read (a reduction over an unrelated buffer) has
@@ -301,7 +326,7 @@ def main():
                 "single_launch_cold_GBps": round(sum(kern_bytes) / (sum(single_ms) / 1e3) / 1e9, 1)}
     del scratch
 
-    extras = {}
+    extras = dict(cold)
     if not args.no_extras:
         for name, fn in (("conjuncts", lambda: conjunct_split(ctx, dt, cps, kern_bytes)),
                          ("plain_latency", lambda: plain_latency(ctx, esc, dg, torch, dev)),
@@ -458,7 +483,29 @@ def plain_latency(ctx, esc, dg, torch, dev, reps=1000):
         c = time.perf_counter()
         tc.append((b - a) * 1e6)
         tm.append((c - b) * 1e6)
-    return {"plain_1M_cpu_baseline": cpu_baseline_plain(t, n),
+    # a materialization with no count before it: single pass (look-back
+    # compaction, a context made with ESC_COLD_COMPACT=1) against count +
+    # scan + write (the default; its workspace's tile record is dropped
+    # before each call, outside the timing)
+    cold = {}
+    os.environ["ESC_COLD_COMPACT"] = "1"
+    ctx1 = esc.Context(0)
+    del os.environ["ESC_COLD_COMPACT"]
+    for name, cx in (("single_pass", ctx1), ("three_pass", ctx)):
+        wsc = torch.zeros(ws.numel(), dtype=torch.uint8, device=dev)
+        tt = []
+        for i in range(reps // 2 + 20):
+            if name == "three_pass":
+                esc.check(esc.lib().esc_workspace_init(cx.h, esc.ctypes.c_void_p(wsc.data_ptr()), wsc.numel(), None))
+                torch.cuda.synchronize()
+            a = time.perf_counter()
+            got = cx.materialize(dt, p, dg.PLAIN_PROJECTION, ids, outs, n, ws=wsc)
+            tt.append((time.perf_counter() - a) * 1e6)
+            assert got == n
+        tt = tt[20:]
+        cold[f"plain_1M_cold_materialize_{name}_us_p50"] = round(float(np.percentile(tt, 50)), 1)
+        cold[f"plain_1M_cold_materialize_{name}_us_p99"] = round(float(np.percentile(tt, 99)), 1)
+    return {"plain_1M_cpu_baseline": cpu_baseline_plain(t, n), **cold,
             "plain_1M_count_us_p50": round(float(np.percentile(tc, 50)), 1),
             "plain_1M_count_us_p99": round(float(np.percentile(tc, 99)), 1),
             "plain_1M_materialize_us_p50": round(float(np.percentile(tm, 50)), 1),

@@ -204,6 +204,11 @@ int esc_ctx_create(int device, esc_ctx **out)
         delete c;
         return hip_fail(e, "hipHostMalloc");
     }
+    if ((e = hipHostGetDevicePointer((void **)&c->pinned_dev, c->pinned, 0)) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return hip_fail(e, "hipHostGetDevicePointer");
+    }
     const char *r = getenv("ESC_COUNT_VARIANT");
     if (r && atoi(r) >= 0 && atoi(r) <= 4) c->count_variant = atoi(r);
     r = getenv("ESC_NONTEMPORAL");
@@ -214,6 +219,8 @@ int esc_ctx_create(int device, esc_ctx **out)
     if (r) c->mat_bpc = atoi(r);
     r = getenv("ESC_DENSE_SHIFT");
     if (r && atoi(r) >= 0 && atoi(r) <= 12) c->dense_shift = atoi(r);
+    r = getenv("ESC_COLD_COMPACT");
+    if (r) c->cold_compact = atoi(r) != 0;
     if (int rc = scratch_address(device, &c->scratch)) {
         (void)hipHostFree(c->pinned);
         delete c;
@@ -326,12 +333,14 @@ int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws,
 {
     if (!out_count) return fail(ESC_ERR_INVALID, "null out_count");
     hipStream_t s = (hipStream_t)stream;
-    WsHeader *h = (WsHeader *)dev_ws;
-    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, h ? &h->result : nullptr, false);
+    // the kernel's last block writes the count straight into pinned host
+    // memory: no copy command between the kernel and the wait (waiting for
+    // the word to change instead of synchronizing the stream measured slower:
+    // 33.7 against 24.1 us per call on a 1M-row table)
+    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx ? ctx->pinned_dev : nullptr, false);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(ctx->pinned, &h->result, 8, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     *out_count = ctx->pinned[0];
     return ESC_OK;
 }
@@ -380,9 +389,37 @@ static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *
         uint32_t *tiles = (uint32_t *)((char *)dev_ws + L.counts_off);
         uint32_t *offsets = (uint32_t *)((char *)dev_ws + L.offsets_off);
         const uint32_t *bits = (const uint32_t *)((char *)dev_ws + L.bits_off);
+        const unsigned long long expect = tiles_stamp(ctx, dev_ws, t, p, rpt);
+        if (!expect && ctx->cold_compact) {
+            // no count came first: count and materialize in one pass
+            const int64_t ntiles = (t->nrows + 64 * kCompactRPT - 1) / (64 * kCompactRPT);
+            const size_t status_off = 256;
+            if (status_off + (size_t)ntiles * 8 > ws_bytes)
+                return fail(ESC_ERR_OOM, "workspace of %zu bytes, %zu needed", ws_bytes, status_off + (size_t)ntiles * 8);
+            forget_tiles(ctx, dev_ws);
+            launch_zero((unsigned long long *)dev_ws, (int64_t)((status_off + (size_t)ntiles * 8) / 8), s);
+            ProjSlots ps;
+            for (int q = 0; q < ESC_MAX_PROJ; q++) {
+                ps.slot[q] = -1;
+                if (q < nproj)
+                    for (int sl = 0; sl < P.nslots; sl++)
+                        if (P.slot_col[sl] == proj_cols[q]) ps.slot[q] = sl;
+            }
+            CompactFn fn = compact_fn(P.nslots, (P.flags & P_HAS_UDF) != 0);
+            const int occ = occupancy((const void *)fn, kScanBlock, 0);
+            int64_t grid = (int64_t)ctx->num_cus * occ;
+            const int64_t blocks_needed = (ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
+            if (grid > blocks_needed) grid = blocks_needed;
+            const uint32_t dense_min = std::max<uint32_t>(1u, (uint32_t)(64 * kCompactRPT) >> ctx->dense_shift);
+            hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt),
+                               t->nrows, (unsigned long long *)((char *)dev_ws + status_off),
+                               (unsigned int *)&h->pad1[0], pa, ps, dev_rowids,
+                               (unsigned long long)(capacity > 0 ? capacity : 0), dense_min, dev_total);
+            hipError_t e = hipGetLastError();
+            return e == hipSuccess ? ESC_OK : hip_fail(e, "compaction kernel launch");
+        }
         // pass 1: per-wave-tile counts and lane masks, unless the preceding
         // count left them (then the launch only checks the workspace's stamp)
-        const unsigned long long expect = tiles_stamp(ctx, dev_ws, t, p, rpt);
         if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true, expect))) return rc;
         // pass 2: offsets in row order (total in h->result)
         launch_scan(tiles, L.ntiles, offsets, h, s);

@@ -24,6 +24,11 @@ struct ProjArgs {
     uint32_t *dst[ESC_MAX_PROJ];
 };
 
+// for each projected column, the predicate slot that holds it, or -1
+struct ProjSlots {
+    int32_t slot[ESC_MAX_PROJ];
+};
+
 // Per-wave-tile results of a count pass, kept for a materialization:
 // counts[t] = qualifying rows of wave tile t; bits[64 t + l] = lane l's
 // truth mask of tile t (bit r = row slot r).
@@ -56,6 +61,11 @@ typedef void (*WriteFn)(const uint32_t *, const uint32_t *, int64_t, const ProjA
                         uint32_t);
 
 CountFn count_fn(int nslots, int ninsn, int variant, bool udf, bool tiles);
+constexpr int kCompactRPT = 16;   // rows per lane of the single-pass compaction
+typedef void (*CompactFn)(const Program, const ColPtrs, int64_t, unsigned long long *, unsigned int *,
+                          const ProjArgs, const ProjSlots, int32_t *, unsigned long long, uint32_t,
+                          unsigned long long *);
+CompactFn compact_fn(int nslots, bool udf);
 int count_rpt(int variant, int nslots, int ninsn, bool tiles);
 int count_bpc(int variant, int nslots, int bpc, bool tiles);
 WriteFn write_fn(int rpt);

@@ -9,11 +9,13 @@ struct esc_ctx {
     int device = 0;
     int num_cus = 0;
     unsigned long long *pinned = nullptr;   // 4 KiB of pinned host memory for read-backs
+    unsigned long long *pinned_dev = nullptr;   // the same memory as the device addresses it
     int count_variant = 4;                  // count kernel shape (see count_rpt / count_bpc)
     int nt = 1;                             // streaming loads in the scans
     int bpc = 1;                            // count-kernel blocks per CU (0: occupancy)
     int mat_bpc = 0;                        // materialize blocks per CU (0: occupancy)
     int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
+    int cold_compact = 0;                   // a materialization without a count first: single pass (1) or count, scan, write (0)
     void *scratch = nullptr;                // this device's static scratch (esc_materialize_noalloc)
 };
 

@@ -228,12 +228,52 @@ __device__ __forceinline__ void stage_and_flush(uint32_t *buf, uint32_t nib, con
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Writes the qualifying rows of one wave tile (lane masks `bits`, rows from
+// `base`) at output positions p onwards, in row order, at most up to `cap`.
+// Chunk j of the tile (256 rows) is compacted in LDS (rank of a row = lanes
+// below, from ballot masks, then e) and each output column is written as one
+// contiguous run.  proj(q, j, e, r0) gives projected column q's value at row
+// r0 + e of chunk j.
+template <int RPT, typename Proj>
+__device__ __forceinline__ void write_tile(uint32_t bits, int64_t base, unsigned long long p, const ProjArgs &pa,
+                                           int32_t *rowids, unsigned long long cap, uint32_t *buf, Proj &&proj)
+{
+    constexpr int NJ = RPT / 4;
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const uint32_t nib = (bits >> (4 * j)) & 0xfu;
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            // set bits of the ballot in the lanes below this one (mbcnt: no
+            // 64-bit shift by a per-lane amount)
+            const uint64_t b = __ballot((nib >> e) & 1u);
+            pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, pre));
+            tot += (uint32_t)__popcll(b);
+        }
+        if (tot == 0) continue;
+        if (p >= cap) break;
+        const uint32_t avail = (uint32_t)(p + tot <= cap ? tot : cap - p);
+        uint32_t slot[4];
+        uint32_t k = pre;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            slot[e] = k;
+            k += (nib >> e) & 1u;
+        }
+        const int64_t r0 = base + (int64_t)j * (4 * kWave) + lane * 4;   // row of e = 0
+        if (rowids)
+            stage_and_flush(buf, nib, slot, [&](int e) { return (uint32_t)(r0 + e); }, (uint32_t *)rowids + p, avail);
+        for (int q = 0; q < pa.nproj; q++) proj(q, j, r0, nib, slot, pa.dst[q] + p, avail);
+        p += tot;
+    }
+}
+
 // Writes the qualifying rows of every wave tile at offsets[t] onwards, in row
-// order, from the lane masks of the count pass.  Chunk j of a wave tile (256
-// rows) is compacted in LDS (rank of a row = lanes below, from ballot masks,
-// then e) and each output column is written as one contiguous run.  A
-// projected column is read with the tile's coalesced 16-byte loads when the
-// tile has at least dense_min qualifying rows, else gathered row by row.
+// order, from the lane masks of the count pass.  A projected column is read
+// with the tile's coalesced 16-byte loads when the tile has at least
+// dense_min qualifying rows, else gathered row by row.
 template <int RPT>
 __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_bits, const uint32_t *offsets,
                                                            int64_t n, const ProjArgs pa, int32_t *rowids,
@@ -241,58 +281,114 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_
 {
     constexpr int TILE = kWave * RPT;
     constexpr int NW = kScanBlock / kWave;
-    constexpr int NJ = RPT / 4;
     __shared__ uint32_t s_buf[NW][4 * kWave];
     uint32_t *buf = s_buf[wave_id()];
     const int64_t ntiles = (n + TILE - 1) / TILE;
     const int64_t step = (int64_t)gridDim.x * NW;
-    const int lane = lane_id();
     for (int64_t t = (int64_t)blockIdx.x * NW + wave_id(); t < ntiles; t += step) {
         const uint32_t o0 = offsets[t], o1 = offsets[t + 1];
         if (o0 == o1 || o0 >= cap) continue;   // wave-uniform
         const int64_t base = t * TILE;
-        const bool full = base + TILE <= n;
-        const bool dense = full && o1 - o0 >= dense_min;
-        const uint32_t bits = tile_bits[t * kWave + lane];
-        unsigned long long p = o0;   // output position of the chunk's first qualifying row
-#pragma unroll
-        for (int j = 0; j < NJ; j++) {
-            const uint32_t nib = (bits >> (4 * j)) & 0xfu;
-            uint32_t pre = 0, tot = 0;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                // set bits of the ballot in the lanes below this one (mbcnt:
-                // no 64-bit shift by a per-lane amount)
-                const uint64_t b = __ballot((nib >> e) & 1u);
-                pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, pre));
-                tot += (uint32_t)__popcll(b);
-            }
-            if (tot == 0) continue;
-            if (p >= cap) break;
-            const uint32_t avail = (uint32_t)(p + tot <= cap ? tot : cap - p);
-            uint32_t slot[4];
-            uint32_t k = pre;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                slot[e] = k;
-                k += (nib >> e) & 1u;
-            }
-            const int64_t r0 = base + (int64_t)j * (4 * kWave) + lane * 4;   // row of e = 0
-            if (rowids)
-                stage_and_flush(buf, nib, slot, [&](int e) { return (uint32_t)(r0 + e); }, (uint32_t *)rowids + p,
-                                avail);
-            for (int q = 0; q < pa.nproj; q++) {
-                const uint32_t *src = pa.src[q];
-                uint32_t *dst = pa.dst[q] + p;
-                if (dense) {
-                    const u32x4 x = __builtin_nontemporal_load((const u32x4 *)(src + r0));
-                    stage_and_flush(buf, nib, slot, [&](int e) { return x[e]; }, dst, avail);
-                } else {
-                    stage_and_flush(buf, nib, slot, [&](int e) { return src[r0 + e]; }, dst, avail);
+        const bool dense = base + TILE <= n && o1 - o0 >= dense_min;
+        const uint32_t bits = tile_bits[t * kWave + lane_id()];
+        write_tile<RPT>(bits, base, o0, pa, rowids, cap, buf,
+                        [&](int q, int, int64_t r0, uint32_t nib, const uint32_t(&slot)[4], uint32_t *dst,
+                            uint32_t avail) {
+                            const uint32_t *src = pa.src[q];
+                            if (dense) {
+                                const u32x4 x = __builtin_nontemporal_load((const u32x4 *)(src + r0));
+                                stage_and_flush(buf, nib, slot, [&](int e) { return x[e]; }, dst, avail);
+                            } else {
+                                stage_and_flush(buf, nib, slot, [&](int e) { return src[r0 + e]; }, dst, avail);
+                            }
+                        });
+    }
+}
+
+// ------------------------------------------------------------------ single-pass compaction
+
+// Status word of a wave tile in the single-pass compaction: flag in the top
+// two bits (0 not yet published, 1 the tile's own count, 2 the inclusive
+// prefix of all tiles up to it), the value in the low 62 bits.
+constexpr unsigned long long kStAggregate = 1ull << 62, kStInclusive = 2ull << 62;
+constexpr unsigned long long kStValue = (1ull << 62) - 1ull;
+
+// Count and materialization in one pass (a materialization with no count
+// before it): waves take wave tiles in increasing order from a counter,
+// evaluate the predicate, publish the tile's count, and find the rows
+// before the tile by looking back over the predecessors' status words (a
+// predecessor that has published its inclusive prefix ends the walk; one
+// that has published only its count adds it and the walk continues).  Every
+// predecessor was taken by a running wave before this tile, so every wait
+// ends.  The qualifying rows are then written at that offset exactly as the
+// write pass does, taking the projected values of predicate columns from
+// registers.  status (ntiles words) and ctr must be zero at launch.
+template <int K, int RPT, bool UDF>
+__global__ __launch_bounds__(kScanBlock) void compact_kernel(const Program P, const ColPtrs cp, int64_t n,
+                                                             unsigned long long *status, unsigned int *ctr,
+                                                             const ProjArgs pa, const ProjSlots ps, int32_t *rowids,
+                                                             unsigned long long cap, uint32_t dense_min,
+                                                             unsigned long long *total)
+{
+    constexpr int TILE = kWave * RPT;
+    constexpr int KK = K > 0 ? K : 1;
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ uint32_t s_buf[NW][4 * kWave];
+    uint32_t *buf = s_buf[wave_id()];
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
+    for (;;) {
+        uint32_t got = 0;
+        if (lane_id() == 0) got = atomicAdd(ctr, 1u);
+        const int64_t t = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+        if (t >= ntiles) break;
+        const int64_t base = t * TILE;
+        uint32_t v[KK][RPT];
+        load_vals<K, RPT>(cp, base, n, v);
+        const uint32_t bits = run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(base, n), tabs);
+        const unsigned long long c = wave_sum((uint32_t)__popc(bits));
+        unsigned long long before = 0;
+        if (t > 0) {
+            __hip_atomic_store(&status[t], kStAggregate | c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int64_t j = t - 1;;) {
+                // every lane reads the same word; its first lane's copy
+                // makes the walk wave-uniform
+                const unsigned long long w =
+                    __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t wlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+                const uint32_t whi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w >> 32));
+                const unsigned long long wu = ((unsigned long long)whi << 32) | wlo;
+                if ((wu >> 62) == 0ull) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
                 }
+                before += wu & kStValue;
+                if ((wu >> 62) == 2ull) break;
+                j--;
             }
-            p += tot;
         }
+        __hip_atomic_store(&status[t], kStInclusive | (before + c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == ntiles - 1 && lane_id() == 0) *total = before + c;
+        if (c == 0 || before >= cap) continue;
+        const bool dense = base + TILE <= n && c >= dense_min;
+        write_tile<RPT>(bits, base, before, pa, rowids, cap, buf,
+                        [&](int q, int j, int64_t r0, uint32_t nib, const uint32_t(&slot)[4], uint32_t *dst,
+                            uint32_t avail) {
+                            const int s = ps.slot[q];
+                            bool done = false;
+                            for_slot<K>(s, [&](auto C) {
+                                stage_and_flush(buf, nib, slot, [&](int e) { return v[C][4 * j + e]; }, dst, avail);
+                                done = true;
+                            });
+                            if (done) return;
+                            const uint32_t *src = pa.src[q];
+                            if (dense) {
+                                const u32x4 x = __builtin_nontemporal_load((const u32x4 *)(src + r0));
+                                stage_and_flush(buf, nib, slot, [&](int e) { return x[e]; }, dst, avail);
+                            } else {
+                                stage_and_flush(buf, nib, slot, [&](int e) { return src[r0 + e]; }, dst, avail);
+                            }
+                        });
     }
 }
 
@@ -362,6 +458,19 @@ ConjFn conj_fn(int nslots, bool udf)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
     return udf ? conj_table_impl<true>(nslots, S{}) : conj_table_impl<false>(nslots, S{});
+}
+
+template <bool UDF, int... Ks>
+constexpr CompactFn compact_table_impl(int k, std::integer_sequence<int, Ks...>)
+{
+    CompactFn t[] = {compact_kernel<Ks, kCompactRPT, UDF>...};
+    return t[k];
+}
+
+CompactFn compact_fn(int nslots, bool udf)
+{
+    using S = std::make_integer_sequence<int, kMaxSlots + 1>;
+    return udf ? compact_table_impl<true>(nslots, S{}) : compact_table_impl<false>(nslots, S{});
 }
 
 WriteFn write_fn(int rpt)

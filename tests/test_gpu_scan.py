@@ -465,3 +465,64 @@ def test_in_bitmaps(ctx, monkeypatch):
         cp = esc.Pred(dt, p)
         assert cp.info()["nhashed"] == 0
         assert ctx.count(dt, cp) == scan.count(t, p), p
+
+
+def _cold_materialize(ctx, dt, p, proj, cap):
+    """A materialization on a fresh workspace (no count before it)."""
+    import torch
+    ws = torch.zeros(ctx.workspace(dt, True, key="cold-size").numel(), dtype=torch.uint8, device="cuda")
+    ids = torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda")
+    outs = [torch.full((max(cap, 1),), -7, dtype=torch.int32, device="cuda").view(dt.cols[j].dtype) for j in proj]
+    c = ctx.materialize(dt, p, proj, ids, outs, cap, ws=ws, allow_overflow=True)
+    k = min(c, cap)
+    return c, ids.cpu().numpy(), [o.cpu().numpy() for o in outs], k
+
+
+@pytest.mark.parametrize("n", [1, 1023, 1024, 1025, 65_537, 1_000_003])
+def test_cold_materialize_single_pass_matches_three_pass(ctx, n, monkeypatch):
+    """A materialization with no count before it, by the single-pass
+    compaction (ESC_COLD_COMPACT=1: look-back over the tiles' published
+    counts) and by the count, scan and write passes (ESC_COLD_COMPACT=0, the
+    default): both and the oracle give the same count, row ids and projected values, every output
+    element past the count untouched, also when the capacity cuts the output
+    short.  Projections mix predicate columns (taken from registers) and
+    others (read from memory)."""
+    monkeypatch.setenv("ESC_COLD_COMPACT", "1")
+    ctx1 = esc.Context(0)
+    monkeypatch.setenv("ESC_COLD_COMPACT", "0")
+    ctx3 = esc.Context(0)
+    rng = np.random.default_rng(700 + n)
+    cols = [np.arange(n, dtype=np.int32), rng.integers(0, 50, n).astype(np.int32),
+            rng.standard_normal(n).astype(np.float32), rng.integers(-3, 4, n).astype(np.int32)]
+    t = dg.Table("cold", n, [dg.INT32, dg.INT32, dg.FLOAT32, dg.INT32], cols, ["u"] * 4, [None] * 4)
+    dt = esc.device_table(t)
+    specs = [("lt", 1, 25), ("and", [("gt", 2, 0.5), ("in", 3, [-2, 1, 3])]), ("eq", 1, 7),
+             ("or", [("between", 0, n // 3, n // 2), ("lt", 2, -1.5)]), ("lt", 0, -1), ("gt", 0, -1)]
+    for i, spec in enumerate(specs):
+        p = esc.Pred(dt, spec)
+        proj = [2, 0, 3] if i % 2 else [1, 3]
+        wc, wids, wouts = scan.materialize(t, spec, proj)
+        for cap in (wc, max(wc // 3, 1)):
+            c1, ids1, outs1, k1 = _cold_materialize(ctx1, dt, p, proj, cap)
+            c3, ids3, outs3, k3 = _cold_materialize(ctx3, dt, p, proj, cap)
+            assert c1 == c3 == wc, (spec, cap)
+            assert np.array_equal(ids1, ids3) and np.array_equal(ids1[:k1], wids[:k1]), (spec, cap)
+            assert (ids1[k1:] == -7).all()
+            for a, b, w in zip(outs1, outs3, wouts):
+                assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+                assert np.array_equal(a[:k1].view(np.uint32), w[:k1].view(np.uint32))
+
+
+def test_cold_materialize_star_all_predicates(ctx, monkeypatch):
+    """The 32 star predicates on 3M rows materialized cold by the single-pass
+    compaction, against the oracle."""
+    monkeypatch.setenv("ESC_COLD_COMPACT", "1")
+    ctx = esc.Context(0)
+    t = dg.table_star(3_000_000, seed=81)
+    dt = esc.device_table(t)
+    for i, spec in enumerate(dg.preds_star(t, 32, seed=82)):
+        p = esc.Pred(dt, spec)
+        wc, wids, wouts = scan.materialize(t, spec, dg.STAR_PROJECTION)
+        c, ids, outs, k = _cold_materialize(ctx, dt, p, dg.STAR_PROJECTION, max(wc, 1))
+        assert c == wc, i
+        assert_same_rows(ids[:c], [o[:c] for o in outs], wids, wouts)
