@@ -337,8 +337,9 @@ int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws,
     // memory: no copy command between the kernel and the wait (waiting for
     // the word to change instead of synchronizing the stream measured slower:
     // 33.7 against 24.1 us per call on a 1M-row table)
-    int rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx ? ctx->pinned_dev : nullptr, false);
+    int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
     if (rc) return rc;
+    if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx->pinned_dev, false))) return rc;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     *out_count = ctx->pinned[0];
