@@ -56,19 +56,18 @@ def pred_columns(spec):
     return cols
 
 
-def counter_traffic():
-    """HBM bytes per count-kernel launch measured with the FETCH_SIZE and
-    WRITE_SIZE counters (profiles/count_kernel_star60M_pmc.txt), or None when
-    the kernel sources changed since the counters were taken."""
+def profile_record(name):
+    """key: value lines of a counter record under profiles/, or None when the
+    kernel sources it names changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "count_kernel_star60M_pmc.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+            kv[k.strip()] = v.split("#")[0].strip()
     h = hashlib.sha256()
     for src in kv.get("kernel_sources", "").split():
         fp = os.path.join(ROOT, src)
@@ -77,7 +76,15 @@ def counter_traffic():
         h.update(open(fp, "rb").read())
     if h.hexdigest() != kv.get("kernel_sources_sha256"):
         return None
-    return int(kv["traffic_bytes_per_launch"])
+    return kv
+
+
+def counter_traffic():
+    """HBM bytes per count-kernel launch measured with the FETCH_SIZE and
+    WRITE_SIZE counters (profiles/count_kernel_star60M_pmc.txt), or None when
+    the kernel sources changed since the counters were taken."""
+    kv = profile_record("count_kernel_star60M_pmc.txt")
+    return int(kv["traffic_bytes_per_launch"]) if kv else None
 
 
 _ORACLE_TABLE = None
@@ -179,6 +186,7 @@ def main():
     ap.add_argument("--sweeps", action="store_true", help="selectivity sweep (2*10^8-row permutation) and "
                                                                "1..5-attribute sweep (star table)")
     ap.add_argument("--typed", action="store_true", help="TEXT / DECIMAL(15,2) predicates (60M rows, 64 predicates)")
+    ap.add_argument("--mlp", action="store_true", help="MLP kernels alone: inference per 4,096 batch, training steps")
     ap.add_argument("--train-preds", type=int, default=200_000)
     ap.add_argument("--queries", type=int, default=1000)
     args = ap.parse_args()
@@ -186,6 +194,8 @@ def main():
         return copy_reference()
     if args.batched:
         return batched_workload()
+    if args.mlp:
+        return mlp_workload()
     if args.learned:
         return learned_workload(args)
     if args.planning:
@@ -445,7 +455,12 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
             "plain_async_predicates_per_s": round(n / tam, 1),
             "batched_speedup_vs_best_plain": round(min(tsm, tam) / tbm, 2),
             "batched_ms": round(tbm * 1e3, 3), "batched_GBps_distinct_columns": round(bytes_batched / tbm / 1e9, 1),
-            "batched_opts": b.opts(), "autotune_s": round(tune_s, 2)}
+            "batched_opts": b.opts(), "autotune_s": round(tune_s, 2),
+            "batched_row_predicates_per_s": round(32 * sum(t.nrows for t in tabs) / tbm, 1),
+            # from the SQ counters of profiles/batch_kernel_256preds_8tables.txt (None once the kernel changed)
+            "batched_valu_issue_fraction": (lambda kv: float(kv["valu_issue_fraction (SQ_INSTS_VALU x 4 / (1024 x "
+                                                            "cycles))"]) if kv else None)(
+                profile_record("batch_kernel_256preds_8tables.txt"))}
 
 
 def cpu_baseline_plain(t, want):
@@ -535,6 +550,54 @@ def copy_reference():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "launches": 3}))
+
+
+def mlp_workload():
+    """The estimator's kernels alone on seeded synthetic features: inference
+    of a 4,096-row batch (one launch) and training steps of 256 and 1,024
+    rows (two kernels and a step advance per step, replayed from a graph),
+    event-timed; TFLOP/s against the bf16 dense MFMA peak."""
+    import torch
+    from paper_1901_01488_amd import datagen as dg
+    from paper_1901_01488_amd import esc
+    torch.cuda.init()
+    ctx = esc.Context(0)
+    m = esc.MLP(ctx, dg.mlp_init(dg.MLP_SEED))
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    x = torch.randn(4096, 64, device="cuda:0", generator=g)
+    out = torch.empty(4096, device="cuda:0")
+    for _ in range(20):
+        m.predict(x, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        m.predict(x, out)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_us = e0.elapsed_time(e1) / 200 * 1e3
+    fwd_flop = 2 * (64 * 256 + 2 * 256 * 256 + 256)
+    res = {"workload": "MLP 64-256-256-256-1, bf16 MFMA / fp32 accumulate",
+           "inference_us_per_4096": round(infer_us, 2),
+           "inference_tflops": round(4096 * fwd_flop / (infer_us * 1e-6) / 1e12, 1),
+           "peak_tflops_bf16_dense": 2500.0}
+    n = 200_000
+    X = torch.randn(n, 64, device="cuda:0", generator=g)
+    Y = torch.randn(n, device="cuda:0", generator=g)
+    for batch in (256, 1024):
+        order = torch.from_numpy(dg.minibatch_order(n, batch, 2, seed=3)).cuda()
+        steps = len(order) // batch
+        m.train(X, Y, order, 10, batch, want_loss=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.train(X, Y, order, steps, batch, want_loss=False)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / steps * 1e6
+        # forward + backward (two input-gradient and three weight-gradient products)
+        flop = batch * (3 * fwd_flop - 2 * 64 * 256)
+        res[f"train_us_per_step_batch{batch}"] = round(us, 1)
+        res[f"train_tflops_batch{batch}"] = round(flop / (us * 1e-6) / 1e12, 2)
+    print(json.dumps(res), flush=True)
 
 
 def learned_workload(args):
