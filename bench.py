@@ -744,23 +744,33 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
         for probe in (0, 1):
             log(f"planning: {kind}, exact_probe {probe}")
             gc = planning.GateConfig(beta=1.5, exact_probe=bool(probe))
+            strict = planning.GateConfig(beta=1.5, exact_probe=bool(probe), tie_sel=0.0)
             modes[(kind, probe)] = (w.run_plain(exact_probe=bool(probe)), w.run_batched(exact_probe=bool(probe)),
-                                    w.run_batched(gate=True, estimators=ests, gcfg=gc))
+                                    w.run_batched(gate=True, estimators=ests, gcfg=gc),
+                                    w.run_batched(gate=True, estimators=ests, gcfg=strict))
     plain = modes[(kinds[0][0], 1)][0]   # counts of all three selections
     count_errors = 0
-    for (kind, probe), (pl, ba, ga) in modes.items():
+    for (kind, probe), (pl, ba, ga, gs) in modes.items():
         cols = [0, 1, 2] if probe else [0, 1]
         count_errors += int((pl["counts"][:, cols] != plain["counts"][:, cols]).sum())
         count_errors += int((ba["counts"][:, cols] != plain["counts"][:, cols]).sum())
-        count_errors += int((ga["counts"][ga["routed"]] != plain["counts"][ga["routed"]]).sum())
-    gcfg = planning.GateConfig(beta=1.5)
-    gated = modes[(kinds[0][0], 0)][2]
-    r = gated["routed"]
+        for g in (ga, gs):
+            count_errors += int((g["counts"][g["routed"]] != plain["counts"][g["routed"]]).sum())
     nrows = [t.nrows for t in tabs]
     exact_sel = plain["counts"] / np.array(nrows, np.float64)
-    est_sel = np.where(r, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
-    agree = np.mean([a == b for a, b in zip(planning.plans(exact_sel, nrows, gcfg),
-                                            planning.plans(est_sel, nrows, gcfg))])
+
+    def agreement(gated, gcfg):
+        r = gated["routed"]
+        est_sel = np.where(r, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
+        ex, es = planning.plans(exact_sel, nrows, gcfg), planning.plans(est_sel, nrows, gcfg)
+        return (float(np.mean([planning.agree(a, b, s, gcfg) for a, b, s in zip(ex, es, exact_sel)])),
+                float(np.mean([a == b for a, b in zip(ex, es)])))
+
+    tie_cfg = planning.GateConfig(beta=1.5)
+    agree_tie, agree_tie_strict = agreement(modes[(kinds[0][0], 0)][2], tie_cfg)
+    agree_strict, _ = agreement(modes[(kinds[0][0], 0)][3], planning.GateConfig(beta=1.5, tie_sel=0.0))
+    empty = [float(np.mean(plain["counts"][:, t] == 0)) for t in range(3)]
+    ties = float(np.mean((exact_sel[:, 0] <= tie_cfg.tie_sel) & (exact_sel[:, 1] <= tie_cfg.tie_sel)))
     # the oracle checks exact counts of R and S (all, or a seeded sample) and
     # a seeded sample of P
     oracle_errors, oracle_checked, oracle_rows, oracle_s, workers = 0, 0, 0, 0.0, 1
@@ -779,12 +789,13 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
     strip = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()
                        if k not in ("counts", "est", "routed")}
     table = {}
-    for (kind, probe), (pl, ba, ga) in modes.items():
+    for (kind, probe), (pl, ba, ga, gs) in modes.items():
         table[f"{kind}_exact_probe{probe}"] = {
-            "plain": strip(pl), "batched": strip(ba), "batched_gate": strip(ga),
+            "plain": strip(pl), "batched": strip(ba), "batched_gate": strip(ga), "batched_gate_no_ties": strip(gs),
             "batched_speedup_vs_plain": round(ba["predicates_per_s"] / pl["predicates_per_s"], 2),
             "gate_speedup_vs_plain": round(ga["predicates_per_s"] / pl["predicates_per_s"], 2),
-            "gate_speedup_vs_batched": round(ga["predicates_per_s"] / ba["predicates_per_s"], 2)}
+            "gate_speedup_vs_batched": round(ga["predicates_per_s"] / ba["predicates_per_s"], 2),
+            "gate_no_ties_speedup_vs_plain": round(gs["predicates_per_s"] / pl["predicates_per_s"], 2)}
     return {
         "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s; "
                     f"estimators trained on {'/'.join(str(v) for v in train_n)} labels, {epochs} epochs",
@@ -793,7 +804,14 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
                 "offered 50x faster; predicates/s counts all three selections of every query",
         "modes": table,
         "count_errors": count_errors,
-        "plan_agreement_with_exact": float(agree), "offline_training_s": round(offline_s, 1),
+        "gate": f"beta 1.5, tau 0.05, join-order ties below selectivity {tie_cfg.tie_sel:g} (no_ties: every order "
+                "counts)",
+        "empty_selection_fraction": [round(v, 3) for v in empty],
+        "queries_with_tied_join_order": round(ties, 3),
+        "plan_agreement_with_exact": round(agree_tie, 4),
+        "plan_agreement_with_exact_ties_compared": round(agree_tie_strict, 4),
+        "plan_agreement_with_exact_no_ties": round(agree_strict, 4),
+        "offline_training_s": round(offline_s, 1),
         "cpu_baseline": {"value": round(oracle_rows / max(oracle_s, 1e-9), 1), "unit": "row-predicates/s",
                          "cores": workers, "kind": "oracle",
                          "sample": f"{'every' if oracle_rs is None else oracle_rs} selection(s) on the 10M and 100M "

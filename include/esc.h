@@ -450,6 +450,16 @@ int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau
  * within a factor beta^2 of each other, so their join order could flip. */
 int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta,
                        uint8_t *route);
+/* esc_gate_join_pair for n queries (yhat_r[i], yhat_s[i] over build
+ * relations of n_r and n_s rows), with ties: when both predicted
+ * selectivities, raised by the error factor beta, are at most tie_sel, the
+ * two join orders differ by at most tie_sel of the probe relation's rows
+ * in the second hash lookup (Section 2.2 joins on the probed input, so the
+ * first join passes sel * |P| rows on), and route[i] = 0 whatever the
+ * order.  tie_sel = 0 disables ties.  Errors: ESC_ERR_INVALID (null
+ * pointers with n > 0, n_r or n_s < 1, beta < 1, tie_sel outside [0, 1]). */
+int esc_gate_join_pairs(const float *yhat_r, int64_t n_r, const float *yhat_s, int64_t n_s, int n,
+                        double beta, double tie_sel, uint8_t *route);
 
 /* ------------------------------------------------------------------ TEXT and DECIMAL columns
  *

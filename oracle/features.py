@@ -252,10 +252,20 @@ def route_pushdown(yhat, n, tau, beta, min_rows):
     return math.log(tau) - math.log(beta) <= s <= math.log(tau) + math.log(beta)
 
 
-def route_join_pair(yhat_r, n_r, yhat_s, n_s, beta):
+def route_join_pair(yhat_r, n_r, yhat_s, n_s, beta, tie_sel=0.0):
     """The build-side join order (smallest filtered relation first; Section
-    2.2) could flip when 1/beta^2 <= c_hat_R / c_hat_S <= beta^2."""
-    lr = log_sel(yhat_r, n_r) + math.log(float(n_r))
-    ls = log_sel(yhat_s, n_s) + math.log(float(n_s))
-    d = lr - ls
+    2.2) could flip when 1/beta^2 <= c_hat_R / c_hat_S <= beta^2.
+
+    Ties: the relation probed first passes sel * |P| of the probe
+    relation's rows on to the second lookup (Section 2.2 probes the largest
+    relation against the others' hash tables), so when both selectivities,
+    even multiplied by beta, are at most tie_sel, the orders differ by at
+    most tie_sel * |P| lookups and neither needs an exact count.  tie_sel =
+    0 turns ties off."""
+    sr, ss = log_sel(yhat_r, n_r), log_sel(yhat_s, n_s)
+    if tie_sel > 0.0:
+        top = math.log(tie_sel) - math.log(beta)
+        if sr <= top and ss <= top:
+            return False
+    d = (sr + math.log(float(n_r))) - (ss + math.log(float(n_s)))
     return -2.0 * math.log(beta) <= d <= 2.0 * math.log(beta)

@@ -366,9 +366,25 @@ int esc_gate_pushdown(const float *yhat, const int64_t *nrows, int n, double tau
 
 int esc_gate_join_pair(float yhat_r, int64_t n_r, float yhat_s, int64_t n_s, double beta, uint8_t *route)
 {
-    if (!route || n_r < 1 || n_s < 1 || !(beta >= 1.0)) return fail(ESC_ERR_INVALID, "bad argument");
-    const double d = (log_sel(yhat_r, n_r) + log((double)n_r)) - (log_sel(yhat_s, n_s) + log((double)n_s));
-    *route = (uint8_t)(-2.0 * log(beta) <= d && d <= 2.0 * log(beta));
+    return esc_gate_join_pairs(&yhat_r, n_r, &yhat_s, n_s, 1, beta, 0.0, route);
+}
+
+int esc_gate_join_pairs(const float *yhat_r, int64_t n_r, const float *yhat_s, int64_t n_s, int n, double beta,
+                        double tie_sel, uint8_t *route)
+{
+    if (n < 0 || (n > 0 && (!yhat_r || !yhat_s || !route))) return fail(ESC_ERR_INVALID, "null argument");
+    if (n_r < 1 || n_s < 1 || !(beta >= 1.0) || !(tie_sel >= 0.0 && tie_sel <= 1.0))
+        return fail(ESC_ERR_INVALID, "need n_r, n_s >= 1, beta >= 1 and 0 <= tie_sel <= 1");
+    const double lb = log(beta);
+    const double lt = tie_sel > 0.0 ? log(tie_sel) : -HUGE_VAL;
+    for (int i = 0; i < n; i++) {
+        const double sr = log_sel(yhat_r[i], n_r), ss = log_sel(yhat_s[i], n_s);
+        const double d = (sr + log((double)n_r)) - (ss + log((double)n_s));
+        // both orders cost the same when neither filtered relation can keep
+        // more than tie_sel of its rows, even at the top of the error band
+        const bool tie = sr + lb <= lt && ss + lb <= lt;
+        route[i] = (uint8_t)(!tie && -2.0 * lb <= d && d <= 2.0 * lb);
+    }
     return ESC_OK;
 }
 

@@ -146,6 +146,8 @@ def lib():
                               ctypes.c_int),
             "esc_gate_pushdown": ([vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp], ctypes.c_int),
             "esc_gate_join_pair": ([ctypes.c_float, i64, ctypes.c_float, i64, ctypes.c_double, vp], ctypes.c_int),
+            "esc_gate_join_pairs": ([vp, i64, vp, i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp],
+                                    ctypes.c_int),
             "esc_ctx_dense_fraction": ([vp, vp], ctypes.c_int),
             "esc_dict_create": ([vp, ctypes.c_int, vp], ctypes.c_int),
             "esc_dict_destroy": ([vp], ctypes.c_int),
@@ -694,6 +696,18 @@ def gate_join_pair(yr, nr, ys, ns, beta):
     r = ctypes.c_uint8()
     check(lib().esc_gate_join_pair(float(yr), int(nr), float(ys), int(ns), float(beta), ctypes.byref(r)))
     return bool(r.value)
+
+
+def gate_join_pairs(yr, nr, ys, ns, beta, tie_sel=0.0):
+    """esc_gate_join_pairs: one route per query (ties: tie_sel)."""
+    a = np.ascontiguousarray(yr, np.float32)
+    b = np.ascontiguousarray(ys, np.float32)
+    if a.shape != b.shape:
+        raise ValueError("yr and ys differ in length")
+    r = np.zeros(len(a), np.uint8)
+    check(lib().esc_gate_join_pairs(a.ctypes.data, int(nr), b.ctypes.data, int(ns), len(a), float(beta),
+                                    float(tie_sel), r.ctypes.data))
+    return r.astype(bool)
 
 
 def policy_keep(model: CostModel, nrows, counts, scan_cols, proj_cols, reuses=1):

@@ -9,6 +9,9 @@ all but the largest relation).  The optimizer needs, per query:
     below the maximum threshold tau and the table has more than min_rows
     rows (Section 2.1);
   - join order: the smaller filtered build relation first (Section 2.2);
+    both orders cost the same when each build relation keeps at most
+    tie_sel of its rows (the relation joined first passes sel * |P| probe
+    rows on to the second lookup), so the order is then left open;
   - no push-down on the probe relation (Section 2.2), so its cardinality
     does not change the plan.
 Every mode takes `exact_probe`: with it off, no mode counts the probe
@@ -33,6 +36,7 @@ class GateConfig:
     min_rows: int = 1_000_000
     beta: float = 1.25
     exact_probe: bool = False
+    tie_sel: float = 1e-3   # 0: every join order counts, however small both relations are
 
 
 def decide(sel_r, sel_s, n_r, n_s, g: GateConfig):
@@ -41,6 +45,15 @@ def decide(sel_r, sel_s, n_r, n_s, g: GateConfig):
     push_s = n_s >= g.min_rows and sel_s < g.tau
     r_first = sel_r * n_r <= sel_s * n_s
     return push_r, push_s, r_first
+
+
+def agree(exact, other, sel_exact, g: GateConfig):
+    """Whether a plan is as good as the exact one: the same push-down
+    decisions and the same join order, unless both build relations of the
+    exact plan keep at most tie_sel of their rows (then both orders cost
+    the same)."""
+    tie = g.tie_sel > 0.0 and sel_exact[0] <= g.tie_sel and sel_exact[1] <= g.tie_sel
+    return exact[0] == other[0] and exact[1] == other[1] and (tie or exact[2] == other[2])
 
 
 class Workload:
@@ -129,9 +142,9 @@ class Workload:
                     est[i:j, t] = yh
                     routed[i:j, t] |= esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows)
                 routed[i:j, 2] = gcfg.exact_probe
-                for q in range(i, j):
-                    if esc.gate_join_pair(est[q, 0], nrows[0], est[q, 1], nrows[1], gcfg.beta):
-                        routed[q, 0] = routed[q, 1] = True
+                pair = esc.gate_join_pairs(est[i:j, 0], nrows[0], est[i:j, 1], nrows[1], gcfg.beta, gcfg.tie_sel)
+                routed[i:j, 0] |= pair
+                routed[i:j, 1] |= pair
                 need = [(q, t) for q in range(i, j) for t in range(3) if routed[q, t]]
             if need:
                 preds = [self.cps[q][t] for q, t in need]

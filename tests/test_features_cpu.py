@@ -67,6 +67,29 @@ def test_gate_matches_oracle():
     assert esc.gate_pushdown(np.array([math.log(0.05)], np.float32), 10**8, 0.05, 1.25, 10**6)[0]
 
 
+def test_join_gate_with_ties_matches_oracle():
+    rng = np.random.default_rng(6)
+    for nr, ns, beta, tie in [(10**7, 10**8, 1.5, 1e-3), (10**7, 10**8, 1.5, 0.0), (10**6, 10**9, 2.0, 1e-2),
+                              (10**8, 10**8, 1.25, 1e-5)]:
+        yr = rng.uniform(-22, 1, 3000).astype(np.float32)
+        ys = rng.uniform(-22, 1, 3000).astype(np.float32)
+        got = esc.gate_join_pairs(yr, nr, ys, ns, beta, tie)
+        want = np.array([fo.route_join_pair(float(a), nr, float(b), ns, beta, tie) for a, b in zip(yr, ys)])
+        assert np.array_equal(got, want)
+        assert 0 < got.sum() < len(got) or tie == 1e-2
+    # ties only remove routes: routed with ties implies routed without
+    yr = rng.uniform(-20, 0, 3000).astype(np.float32)
+    ys = rng.uniform(-20, 0, 3000).astype(np.float32)
+    with_tie = esc.gate_join_pairs(yr, 10**7, ys, 10**8, 1.5, 1e-3)
+    without = esc.gate_join_pairs(yr, 10**7, ys, 10**8, 1.5, 0.0)
+    assert not (with_tie & ~without).any() and (without & ~with_tie).any()
+    assert len(esc.gate_join_pairs(np.zeros(0, np.float32), 10, np.zeros(0, np.float32), 10, 1.5, 0.0)) == 0
+    with pytest.raises(esc.EscError):
+        esc.gate_join_pairs(yr, 10**7, ys, 10**8, 1.5, 2.0)
+    with pytest.raises(esc.EscError):
+        esc.gate_join_pairs(yr, 0, ys, 10**8, 1.5, 0.0)
+
+
 def test_catalog_handle_matches_featurize():
     """Features from a catalog built once equal esc_featurize's bit for bit."""
     from paper_1901_01488_amd import learned

@@ -227,6 +227,29 @@ def test_gate_join_pair():
     assert not fo.route_join_pair(yr, 10**7, ys2, 10**8, beta)
 
 
+def test_gate_join_tie():
+    beta = 1.5
+    # c_R = 1000 of 10^7 (sel 1e-4), c_S = 2000 of 10^8 (sel 2e-5): the
+    # orders could flip (ratio 0.5 >= 1/beta^2), but at the top of the band
+    # the selectivities are 1.5e-4 and 3e-5, both below tie_sel = 1e-3
+    yr = math.log(1000 / 10**7)
+    ys = math.log(2000 / 10**8)
+    assert fo.route_join_pair(yr, 10**7, ys, 10**8, beta, tie_sel=0.0)
+    assert not fo.route_join_pair(yr, 10**7, ys, 10**8, beta, tie_sel=1e-3)
+    # tie_sel = 1e-4: R's band reaches 1.5e-4 > 1e-4, so the pair is routed
+    assert fo.route_join_pair(yr, 10**7, ys, 10**8, beta, tie_sel=1e-4)
+    # boundary: R's selectivity times beta exactly tie_sel is a tie
+    yr_edge = math.log(1e-3 / beta)
+    ys_edge = math.log(1e-3 / beta) + math.log(10**7 / 10**8)   # same filtered size as R
+    assert not fo.route_join_pair(yr_edge, 10**7, ys_edge, 10**8, beta, tie_sel=1e-3 * (1 + 1e-12))
+    assert fo.route_join_pair(yr_edge, 10**7, ys_edge, 10**8, beta, tie_sel=1e-3 * (1 - 1e-9))
+    # two empty selections (estimates clamped to one row each): equal
+    # filtered sizes route without ties, and are a tie once tie_sel >= beta / n
+    assert fo.route_join_pair(-50.0, 10**7, -50.0, 10**8, beta)
+    assert not fo.route_join_pair(-50.0, 10**7, -50.0, 10**7, beta, tie_sel=1e-6)
+    assert fo.route_join_pair(-50.0, 10**7, -50.0, 10**7, beta, tie_sel=0.0)
+
+
 def test_huber_loss_values():
     # e^2 / 2 inside the threshold 1/2, 1/2 (|e| - 1/4) beyond; continuous at |e| = 1/2
     assert mlp.loss(np.array([0.25]), np.array([0.0])) == 0.03125
