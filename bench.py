@@ -353,7 +353,10 @@ def main():
         # planning estimators trained on fewer labels, capacity runs only
         for name, fn in (("learned", lambda: learned_leg(ctx, 200_000, oracle_random=100, oracle_routed=100)),
                          ("planning", lambda: planning_leg(ctx, 1000, train_n=(20_000, 20_000, 4_000), epochs=20,
-                                                           offered=False, oracle_rs=32, oracle_p=0))):
+                                                           offered=False, oracle_rs=32, oracle_p=0)),
+                         ("planning_nonempty", lambda: planning_leg(ctx, 1000, train_n=(20_000, 20_000, 4_000),
+                                                                    epochs=20, offered=False, oracle_rs=32,
+                                                                    oracle_p=0, gen="anchored"))):
             try:
                 log(f"extra: {name}")
                 extras[name] = fn()
@@ -705,14 +708,26 @@ def planning_workload(args):
     ctx = esc.Context(0)
     r = planning_leg(ctx, args.queries, train_n=(100_000, 100_000, 20_000), epochs=20, offered=True,
                      oracle_rs=None, oracle_p=48)
-    print(json.dumps(r), flush=True)
+    r2 = planning_leg(ctx, args.queries, train_n=(100_000, 100_000, 20_000), epochs=20, offered=False,
+                      oracle_rs=None, oracle_p=48, gen="anchored")
+    print(json.dumps({"planning": r, "planning_nonempty": r2}), flush=True)
 
 
-def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
+def planning_queries(dg, table, count, seed, gen):
+    """Selections of one table: `mixed` = 2-6 conjuncts with random
+    constants (most select nothing), `anchored` = 2-4 conjuncts on distinct
+    columns built around a sampled row (every selection keeps >= 1 row)."""
+    if gen == "anchored":
+        return dg.preds_anchored(table, count, seed=seed, min_conj=2, max_conj=4)
+    return dg.preds_mixed(table, count, seed=seed, min_conj=2, max_conj=6)
+
+
+def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p, gen="mixed"):
     """nq arriving three-table queries (10M / 100M / 1B rows): plain
     per-selection counts vs micro-batched graph launches vs batched + gate,
     every mode on the same work.  oracle_rs: selections of R and S the oracle
-    checks (None = all); oracle_p: selections of P it checks."""
+    checks (None = all); oracle_p: selections of P it checks; gen: the query
+    generator (planning_queries)."""
     import torch
     from paper_1901_01488_amd import datagen as dg
     from paper_1901_01488_amd import esc, learned, planning
@@ -720,14 +735,14 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
     log("planning: tables")
     tabs = dg.tables_planning(device=dev)
     dts = [esc.Table(t.nrows, t.dtypes, t.cols) for t in tabs]
-    qs = [dg.preds_mixed(t, nq, seed=dg.pred_seed(4) + i, min_conj=2, max_conj=6) for i, t in enumerate(tabs)]
+    qs = [planning_queries(dg, t, nq, dg.pred_seed(4) + i, gen) for i, t in enumerate(tabs)]
     queries = list(zip(*qs))
     arrivals = dg.poisson_arrivals(nq, 2000.0, seed=dg.pred_seed(4))
     ests = []
     t0 = time.perf_counter()
     for i, (t, dt) in enumerate(zip(tabs, dts)):
         log(f"planning: estimator {i}")
-        specs = dg.preds_mixed(t, train_n[i], seed=dg.pred_seed(4) + 100 + i, min_conj=2, max_conj=6)
+        specs = planning_queries(dg, t, train_n[i], dg.pred_seed(4) + 100 + i, gen)
         cps = [esc.Pred(dt, p) for p in specs]
         cnt = learned.exact_counts(ctx, dt, cps)
         e = learned.Estimator(ctx, dt, learned.Catalog.of(t, seed=11 + i), dg.mlp_init(dg.MLP_SEED))
@@ -798,6 +813,7 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p):
             "gate_no_ties_speedup_vs_plain": round(gs["predicates_per_s"] / pl["predicates_per_s"], 2)}
     return {
         "workload": f"planning: {nq} three-table queries over 10M / 100M / 1B rows, Poisson arrivals 2000/s; "
+                    f"selections: {'2-4 conjuncts around a sampled row' if gen == 'anchored' else '2-6 conjuncts, random constants'}; "
                     f"estimators trained on {'/'.join(str(v) for v in train_n)} labels, {epochs} epochs",
         "note": "every mode does the same work: exact_probe0 = no mode counts the probe relation's selection "
                 "(no plan depends on it), exact_probe1 = every mode counts it; capacity = the same queries "
