@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define ESC_ABI_VERSION 7
+#define ESC_ABI_VERSION 8
 
 /* Column types.  DATE32 is int32 days since 1970-01-01, compared as int32. */
 typedef enum { ESC_INT32 = 0, ESC_DATE32 = 1, ESC_FLOAT32 = 2 } esc_dtype;
@@ -312,7 +312,10 @@ typedef struct {
     int32_t chunk_rows;      /* rows per work item; 0 = about 8 items per block of the grid */
     int32_t blocks_per_cu;   /* persistent blocks per compute unit; 0 = default */
     int32_t max_preds;       /* predicates the batch may hold after esc_batch_update; 0 = npreds */
-    int32_t pad;
+    int32_t max_cols;        /* distinct columns a predicate group loads per tile: 4, 6 or 8 (fewer
+                                register slots let more waves share a SIMD); 0 = the smallest that
+                                holds every predicate; other values = 0.  Autotuning tries that
+                                smallest and 8 */
 } esc_batch_opts;
 
 /* Workspace bytes of a batch of these predicates over these tables: room
@@ -331,10 +334,11 @@ int esc_batch_create(esc_ctx *ctx, const esc_table *const *tables, int ntables,
 /* Loads autotuner choices from a file written by earlier runs (the file that
  * the ESC_AUTOTUNE_CACHE environment variable names is loaded the same way
  * at the first autotuned esc_batch_create).  One entry per line: a key and
- * five integers (block, rows per thread, group, chunk rows, blocks per CU);
- * entries whose values a batch would not accept (block other than 256,
- * rows per thread other than 8 or 16, negative group, chunk rows or blocks
- * per CU) are skipped.  *accepted / *rejected (either may be NULL) count the
+ * five or six integers (block, rows per thread, group, chunk rows, blocks
+ * per CU, and max_cols, 0 when absent); entries whose values a batch would
+ * not accept (block other than 256, rows per thread other than 8 or 16,
+ * negative group, chunk rows or blocks per CU, max_cols other than 0, 4, 6
+ * or 8) are skipped.  *accepted / *rejected (either may be NULL) count the
  * lines kept and skipped.  Host only.  Errors: ESC_ERR_INVALID (null path or
  * unreadable file). */
 int esc_batch_tune_cache_load(const char *path, int *accepted, int *rejected);

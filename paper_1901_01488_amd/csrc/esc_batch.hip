@@ -53,32 +53,82 @@ struct BatchItem {
     int32_t pad;
 };
 
-// The waves of a block walk the item's wave tiles independently; each wave
-// tile is loaded once and every predicate of the group runs on it.
-template <int K, int RPT, bool UDF>
-__device__ __forceinline__ void run_item(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
-                                         uint32_t (*s_cnt)[kScanBlock / 64])
+// Column pointers of a group come out of device memory, so the compiler
+// cannot tell that they point to global memory and would emit flat loads
+// (which also hold back every scalar-memory wait of the interpreter); the
+// casts make them global loads.
+typedef const uint32_t __attribute__((address_space(1))) gu32;
+typedef const u32x4 __attribute__((address_space(1))) gu32x4;
+
+// The columns of a full wave tile of the group starting at row `base`.
+template <int K, int RPT>
+__device__ __forceinline__ void load_tile(const BatchGroup &g, int64_t base, uint32_t (&v)[K][RPT])
 {
-    constexpr int TILE = kWave * RPT;
-    constexpr int NW = kScanBlock / kWave;
-    const int wave = wave_id();
-    ColPtrs cp{};
-    cp.nt = 1;
 #pragma unroll
-    for (int c = 0; c < K; c++) cp.p[c] = g.cols[c];
-    const int npred = g.npred;
-    for (int64_t base = it.r0 + (int64_t)wave * TILE; base < it.r1; base += (int64_t)NW * TILE) {
-        uint32_t v[K][RPT];
-        load_vals<K, RPT>(cp, base, it.r1, v);
-        const uint32_t valid = valid_bits<RPT>(base, it.r1);
-        for (int i = 0; i < npred; i++) {
-            const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(progs[g.pbegin + i], v, valid)));
-            if (lane_id() == 0) s_cnt[i][wave] += c;
+    for (int j = 0; j < RPT / 4; j++) {
+        const int64_t idx = base + (int64_t)j * (4 * kWave) + lane_id() * 4;
+#pragma unroll
+        for (int c = 0; c < K; c++) {
+            const u32x4 q = __builtin_nontemporal_load((gu32x4 *)((gu32 *)g.cols[c] + idx));
+            v[c][4 * j + 0] = q.x;
+            v[c][4 * j + 1] = q.y;
+            v[c][4 * j + 2] = q.z;
+            v[c][4 * j + 3] = q.w;
         }
     }
 }
 
-template <int RPT, bool UDF>
+// Every predicate of the group on one tile; counts into s_cnt.
+template <int K, int RPT, bool UDF>
+__device__ __forceinline__ void run_tile(const Program *gp, int npred, const uint32_t (&v)[K][RPT], uint32_t valid,
+                                         uint32_t (*s_cnt)[kScanBlock / 64], int wave)
+{
+    for (int i = 0; i < npred; i++) {
+        const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(gp[i], v, valid)));
+        if (lane_id() == 0) s_cnt[i][wave] += c;
+    }
+}
+
+// The waves of a block walk the item's full wave tiles independently; each
+// tile is loaded once and every predicate of the group runs on it.  The
+// rows after the last full tile (fewer than one tile) are taken in tiles of
+// four rows per lane, with bounds checks: kept apart, their code does not
+// add to the registers of the main loop.
+template <int K, int RPT, bool UDF>
+__device__ __forceinline__ void run_group(const BatchGroup &g, const BatchItem &it, const Program *__restrict__ progs,
+                                          uint32_t (*s_cnt)[kScanBlock / 64])
+{
+    constexpr int TILE = kWave * RPT;
+    constexpr int NW = kScanBlock / kWave;
+    const int wave = wave_id();
+    const int npred = g.npred;
+    const Program *gp = progs + g.pbegin;
+    const int64_t full_end = it.r0 + (it.r1 - it.r0) / TILE * TILE;
+    for (int64_t base = it.r0 + (int64_t)wave * TILE; base < full_end; base += (int64_t)NW * TILE) {
+        uint32_t v[K][RPT];
+        load_tile<K, RPT>(g, base, v);
+        run_tile<K, RPT, UDF>(gp, npred, v, all_rows<RPT>(), s_cnt, wave);
+    }
+    constexpr int T4 = kWave * 4;
+    for (int64_t base = full_end + (int64_t)wave * T4; base < it.r1; base += (int64_t)NW * T4) {
+        const uint32_t rem = (uint32_t)(it.r1 - base);   // < TILE: 32-bit offsets
+        const uint32_t off = (uint32_t)lane_id() * 4u;
+        uint32_t v[K][4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+#pragma unroll
+            for (int c = 0; c < K; c++) v[c][r] = off + r < rem ? ((gu32 *)g.cols[c] + base)[off + r] : 0u;
+        }
+        const uint32_t valid = (off < rem ? 1u : 0u) | (off + 1 < rem ? 2u : 0u) | (off + 2 < rem ? 4u : 0u) |
+                               (off + 3 < rem ? 8u : 0u);
+        run_tile<K, 4, UDF>(gp, npred, v, valid, s_cnt, wave);
+    }
+}
+
+// One persistent kernel per (rows per lane, udf support, column slots KM):
+// a group's K <= KM columns are dispatched to a body compiled for K, so the
+// kernel's registers (and the waves a SIMD holds) follow from KM.
+template <int RPT, bool UDF, int KM>
 __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__restrict__ groups,
                                                            const BatchItem *__restrict__ items,
                                                            const Program *__restrict__ progs,
@@ -98,16 +148,25 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
         const BatchItem it = items[item];
         const BatchGroup &g = groups[it.group];
         switch (g.K) {
-        case 1: run_item<1, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 2: run_item<2, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 3: run_item<3, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 4: run_item<4, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 5: run_item<5, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 6: run_item<6, RPT, UDF>(g, it, progs, s_cnt); break;
-        case 7: run_item<7, RPT, UDF>(g, it, progs, s_cnt); break;
-        default: run_item<8, RPT, UDF>(g, it, progs, s_cnt); break;
-        }
-        __syncthreads();
+        case 1: run_group<1, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 2: run_group<2, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 3: run_group<3, RPT, UDF>(g, it, progs, s_cnt); break;
+        case 4: run_group<4, RPT, UDF>(g, it, progs, s_cnt); break;
+        default:
+            if constexpr (KM >= 6) {
+                switch (g.K) {
+                case 5: run_group<5, RPT, UDF>(g, it, progs, s_cnt); break;
+                case 6: run_group<6, RPT, UDF>(g, it, progs, s_cnt); break;
+                default:
+                    if constexpr (KM >= 8) {
+                        if (g.K == 7) run_group<7, RPT, UDF>(g, it, progs, s_cnt);
+                        else run_group<8, RPT, UDF>(g, it, progs, s_cnt);
+                    }
+                    break;
+                }
+            }
+            break;
+        }        __syncthreads();
         for (int i = threadIdx.x; i < g.npred; i += kScanBlock) {
             unsigned long long s = 0;
 #pragma unroll
@@ -124,10 +183,16 @@ __global__ __launch_bounds__(kScanBlock) void batch_kernel(const BatchGroup *__r
 typedef void (*BatchFn)(const BatchGroup *, const BatchItem *, const Program *, const int32_t *,
                         unsigned long long *, unsigned int *);
 
-static BatchFn batch_fn(int rpt, bool udf)
+template <int KM>
+static BatchFn batch_fn_km(int rpt, bool udf)
 {
-    if (rpt == 16) return udf ? batch_kernel<16, true> : batch_kernel<16, false>;
-    return udf ? batch_kernel<8, true> : batch_kernel<8, false>;
+    if (rpt == 16) return udf ? batch_kernel<16, true, KM> : batch_kernel<16, false, KM>;
+    return udf ? batch_kernel<8, true, KM> : batch_kernel<8, false, KM>;
+}
+
+static BatchFn batch_fn(int rpt, bool udf, int km)
+{
+    return km <= 4 ? batch_fn_km<4>(rpt, udf) : km <= 6 ? batch_fn_km<6>(rpt, udf) : batch_fn_km<8>(rpt, udf);
 }
 
 __global__ void batch_zero_kernel(unsigned long long *counts, int n, unsigned int *queue)
@@ -201,6 +266,16 @@ Program remap(const Program &P, const int *gslot_of_col, int K, const int *gcols
     return Q;
 }
 
+// Column slots of the kernel a batch uses: the smallest of 4, 6 and 8 that
+// holds max_cols and every scanned predicate's columns.
+int slot_limit(const esc_batch *b, const esc_batch_opts &o)
+{
+    int need = std::max(1, (int)o.max_cols);
+    for (size_t p = 0; p < b->src.size(); p++)
+        if (b->constant[p] == 0) need = std::max(need, (int)b->src[p].nslots);
+    return need <= 4 ? 4 : need <= 6 ? 6 : 8;
+}
+
 // chunk_rows == 0 sizes the chunks so that the plan has about eight items
 // per block of the persistent grid (load balance at the end of the launch),
 // but no fewer than 8 block tiles per item (the per-item cost of the atomic
@@ -226,6 +301,7 @@ int build_plan(const esc_batch *b, const esc_batch_opts &o, int grid, Plan &plan
 {
     plan = Plan{};
     const int gmax = o.group > 0 ? std::min(o.group, kMaxGroup) : kMaxGroup;
+    const int kmax = slot_limit(b, o);
     const int64_t chunk = chunk_rows_for(b, o, gmax, grid);
     struct Cost { int64_t cost; BatchItem it; };
     std::vector<Cost> items;
@@ -245,7 +321,7 @@ int build_plan(const esc_batch *b, const esc_batch_opts &o, int grid, Plan &plan
                 const Program &P = b->src[members[i]];
                 int add = 0;
                 for (int s = 0; s < P.nslots; s++) add += gslot[P.slot_col[s]] < 0;
-                if (K + add > kMaxSlots) break;
+                if (K + add > kmax) break;
                 for (int s = 0; s < P.nslots; s++)
                     if (gslot[P.slot_col[s]] < 0) { gslot[P.slot_col[s]] = K; gcols[K++] = P.slot_col[s]; }
                 mem.push_back(members[i]);
@@ -301,6 +377,7 @@ esc_batch_opts normalized(const esc_batch_opts *opts)
     if (opts) o = *opts;
     if (o.rows_per_thread != 16) o.rows_per_thread = 8;
     o.block = kScanBlock;
+    if (o.max_cols != 4 && o.max_cols != 6 && o.max_cols != 8) o.max_cols = 0;
     if (o.group < 0) o.group = 0;
     if (o.chunk_rows < 0) o.chunk_rows = 0;
     if (o.blocks_per_cu < 0) o.blocks_per_cu = 0;
@@ -325,7 +402,7 @@ BatchFn batch_kernel_for(const esc_batch *b, const esc_batch_opts &o)
 {
     bool udf = false;
     for (size_t p = 0; p < b->src.size(); p++) udf |= b->constant[p] == 0 && (b->src[p].flags & P_HAS_UDF) != 0;
-    return batch_fn(o.rows_per_thread, udf);
+    return batch_fn(o.rows_per_thread, udf, slot_limit(b, o));
 }
 
 // Persistent grid of a launch: blocks per CU as asked, at most what fits
@@ -344,29 +421,35 @@ bool cached_tune(const std::string &key, esc_batch_opts *out);
 // themselves, or with autotuning every candidate the tuner times (rows per
 // thread x group size x chunk length) and a choice cached for these tables
 // and predicates.
-std::vector<esc_batch_opts> tuner_candidates()
+std::vector<esc_batch_opts> tuner_candidates(const esc_batch *b)
 {
     std::vector<esc_batch_opts> out;
     const int rpts[] = {16, 8};
     const int groups[] = {0, 16, 8};
     const int chunks[] = {0, 1 << 17, 1 << 20};   // 0: sized to the grid
-    for (int rpt : rpts)
-        for (int grp : groups)
-            for (int ch : chunks) {
-                esc_batch_opts c{};
-                c.block = kScanBlock;
-                c.rows_per_thread = rpt;
-                c.group = grp;
-                c.chunk_rows = ch;
-                out.push_back(c);
-            }
+    esc_batch_opts least{};
+    const int kmin = slot_limit(b, least);
+    for (int km : {kmin, 8}) {
+        for (int rpt : rpts)
+            for (int grp : groups)
+                for (int ch : chunks) {
+                    esc_batch_opts c{};
+                    c.block = kScanBlock;
+                    c.rows_per_thread = rpt;
+                    c.group = grp;
+                    c.chunk_rows = ch;
+                    c.max_cols = km;
+                    out.push_back(c);
+                }
+        if (kmin == 8) break;
+    }
     return out;
 }
 
 std::vector<esc_batch_opts> candidates(const esc_batch *b, const esc_batch_opts &o)
 {
     if (!o.autotune) return {o};
-    std::vector<esc_batch_opts> out = tuner_candidates();
+    std::vector<esc_batch_opts> out = tuner_candidates(b);
     esc_batch_opts cached{};
     if (cached_tune(tune_key(b), &cached)) out.push_back(cached);
     return out;
@@ -398,6 +481,7 @@ int install(esc_batch *b, const esc_batch_opts &o)
     b->nitems = (int)nitems;
     b->opts = o;
     b->opts.blocks_per_cu = grid / std::max(1, b->ctx->num_cus);
+    b->opts.max_cols = slot_limit(b, o);
     // the graph bakes in the workspace regions (fixed for the batch's
     // lifetime), the counter capacity and the kernel
     const bool reuse = b->exec && grid == b->grid && b->graph_fn == (const void *)fn;
@@ -455,12 +539,13 @@ std::string tune_key(const esc_batch *b)
 bool acceptable(const esc_batch_opts &o)
 {
     return o.block == kScanBlock && (o.rows_per_thread == 8 || o.rows_per_thread == 16) && o.group >= 0 &&
-           o.chunk_rows >= 0 && o.blocks_per_cu >= 0;
+           o.chunk_rows >= 0 && o.blocks_per_cu >= 0 &&
+           (o.max_cols == 0 || o.max_cols == 4 || o.max_cols == 6 || o.max_cols == 8);
 }
 
-// Reads "key block rpt group chunk bpc" lines into the in-process cache;
-// lines that do not parse or hold options a batch would not accept are
-// skipped.  Needs g_tune_mu.
+// Reads "key block rpt group chunk bpc [max_cols]" lines into the
+// in-process cache; lines that do not parse or hold options a batch would
+// not accept are skipped.  Needs g_tune_mu.
 int read_tune_file(const char *path, int *accepted, int *rejected)
 {
     FILE *f = fopen(path, "r");
@@ -471,10 +556,10 @@ int read_tune_file(const char *path, int *accepted, int *rejected)
         char key[4096];
         esc_batch_opts o{};
         char extra[2];
-        const int n = sscanf(line, "%4095s %d %d %d %d %d %1s", key, &o.block, &o.rows_per_thread, &o.group,
-                             &o.chunk_rows, &o.blocks_per_cu, extra);
+        const int n = sscanf(line, "%4095s %d %d %d %d %d %d %1s", key, &o.block, &o.rows_per_thread, &o.group,
+                             &o.chunk_rows, &o.blocks_per_cu, &o.max_cols, extra);
         if (n <= 0) continue;   // blank line
-        if (n == 6 && acceptable(o)) {
+        if ((n == 6 || n == 7) && acceptable(o)) {
             g_tune_cache[key] = o;
             ok++;
         } else {
@@ -503,8 +588,8 @@ void save_tune(const std::string &key, const esc_batch_opts &o)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
-            o.blocks_per_cu);
+    fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), o.block, o.rows_per_thread, o.group, o.chunk_rows,
+            o.blocks_per_cu, o.max_cols);
     fclose(f);
 }
 
@@ -538,7 +623,7 @@ int autotune(esc_batch *b, hipStream_t s)
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(ESC_ERR_HIP, "hipEventCreate failed");
     int rc = ESC_OK;
-    for (const esc_batch_opts &o : tuner_candidates()) {
+    for (const esc_batch_opts &o : tuner_candidates(b)) {
                 if ((rc = install(b, o))) goto done;
                 if ((rc = run(b, s, got.data()))) goto done;
                 if (!have_ref) { ref = got; have_ref = true; }

@@ -74,11 +74,11 @@ class CostModel(ctypes.Structure):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("autotune", ctypes.c_int32), ("block", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("chunk_rows", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("max_preds", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("max_preds", ctypes.c_int32), ("max_cols", ctypes.c_int32)]
 
 
 WS_COUNT, WS_MATERIALIZE, WS_CONJUNCTS = 0, 1, 2   # esc_workspace_size kinds
-ABI_VERSION = 7   # esc.h's ESC_ABI_VERSION for the struct layouts below
+ABI_VERSION = 8   # esc.h's ESC_ABI_VERSION for the struct layouts below
 
 _lib = None
 
@@ -459,11 +459,11 @@ class Batch:
     on a larger one."""
 
     def __init__(self, ctx: Context, tables, preds, owner, autotune=False, rows_per_thread=0, group=0,
-                 chunk_rows=0, blocks_per_cu=0, max_preds=0, stream=None):
+                 chunk_rows=0, blocks_per_cu=0, max_preds=0, max_cols=0, stream=None):
         self.ctx = ctx
         self.tables = list(tables)
         self._o = BatchOpts(1 if autotune else 0, 0, rows_per_thread, group, chunk_rows, blocks_per_cu,
-                            max_preds, 0)
+                            max_preds, max_cols)
         self.h = None
         self._create(preds, owner, stream)
 
@@ -507,7 +507,7 @@ class Batch:
         o = BatchOpts()
         check(lib().esc_batch_get_opts(self.h, ctypes.byref(o)))
         return {"rows_per_thread": o.rows_per_thread, "group": o.group, "chunk_rows": o.chunk_rows,
-                "blocks_per_cu": o.blocks_per_cu}
+                "blocks_per_cu": o.blocks_per_cu, "max_cols": o.max_cols}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

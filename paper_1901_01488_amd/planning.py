@@ -150,7 +150,10 @@ class Workload:
                 preds = [self.cps[q][t] for q, t in need]
                 owners = [t for _, t in need]
                 if self.batch is None:
-                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16,
+                    # 16 rows per lane, groups of 16 predicates, the
+                    # kernel with four column slots (the tables have four
+                    # columns): the fastest measured for these windows
+                    self.batch = esc.Batch(self.ctx, self.tables, preds, owners, rows_per_thread=16, group=16,
                                            max_preds=3 * window)
                 else:
                     self.batch.update(preds, owners)

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 30
     missing = [s for s in syms if not hasattr(L, s)]
     assert not missing, missing
-    assert L.esc_abi_version() == 7
+    assert L.esc_abi_version() == 8
 
 
 @pytest.fixture(scope="module")
@@ -224,7 +224,8 @@ def test_in_slot_tables(schema, monkeypatch):
 def test_autotune_cache_file_skips_bad_entries(tmp_path):
     """Tuning-cache lines whose options a batch would not accept (rows per
     thread other than 8 or 16, a block other than 256, negative group, chunk
-    or blocks per CU, missing or extra fields) are skipped, not installed."""
+    or blocks per CU, max_cols other than 0, 4, 6 or 8, missing or extra
+    fields) are skipped, not installed."""
     L = esc.lib()
     f = tmp_path / "tune.txt"
     f.write_text("k1 256 16 0 0 0\n"
@@ -236,8 +237,12 @@ def test_autotune_cache_file_skips_bad_entries(tmp_path):
                  "junk\n"
                  "\n"
                  "k7 256 8 16 131072 2\n"
-                 "k8 256 8 0 0 0 9\n")
+                 "k8 256 8 0 0 0 9\n"          # max_cols 9
+                 "k9 256 16 0 0 0 4\n"
+                 "k10 256 16 0 0 2 6\n"
+                 "k11 256 16 0 0 2 5\n"        # max_cols 5
+                 "k12 256 16 0 0 2 8 1\n")     # an extra field
     acc, rej = ctypes.c_int(-1), ctypes.c_int(-1)
     assert L.esc_batch_tune_cache_load(str(f).encode(), ctypes.byref(acc), ctypes.byref(rej)) == esc.OK
-    assert (acc.value, rej.value) == (2, 7)
+    assert (acc.value, rej.value) == (4, 9)
     assert L.esc_batch_tune_cache_load(str(tmp_path / "missing").encode(), None, None) == esc.ERR_INVALID

@@ -28,7 +28,9 @@ def small_batch():
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(rows_per_thread=16), dict(group=5, chunk_rows=4096),
-                                  dict(group=1, chunk_rows=1 << 20, rows_per_thread=16), dict(blocks_per_cu=1)])
+                                  dict(group=1, chunk_rows=1 << 20, rows_per_thread=16), dict(blocks_per_cu=1),
+                                  dict(rows_per_thread=16, max_cols=8), dict(rows_per_thread=16, max_cols=6),
+                                  dict(max_cols=6, group=3, chunk_rows=8192)])
 def test_batched_equals_oracle_small(ctx, small_batch, opts):
     tabs, preds, owner = small_batch
     dts = [esc.device_table(t) for t in tabs]
@@ -145,3 +147,37 @@ def test_batched_update_beyond_capacity_is_refused(ctx, small_batch):
     assert b.count().tolist() == want8
     b.update(cps[:12], owner[:12])
     assert b.count().tolist() == [scan.count(tabs[o], p) for p, o in zip(preds[:12], owner[:12])]
+
+
+@pytest.mark.parametrize("max_cols,rpt", [(4, 16), (4, 8), (6, 16), (8, 16), (0, 16)])
+def test_column_slot_limits(ctx, max_cols, rpt):
+    """Groups limited to 4, 6 or 8 distinct columns (kernels with fewer
+    register slots run more waves per SIMD): predicates over at most four
+    columns of 4- to 8-column tables, with udfs in some, split into more
+    groups than with eight slots; every count equals the oracle's, and a
+    predicate needing more slots than asked raises the limit."""
+    tabs = dg.tables_batched([3_000, 70_001, 400_000, 1_100_000])
+    rng = np.random.default_rng(40 + max_cols)
+    preds, owner = [], []
+    for ti, t in enumerate(tabs):
+        for p in dg.preds_mixed(t, 24, seed=int(rng.integers(1 << 30)), min_conj=1, max_conj=4, p_or=0.0):
+            preds.append(p)
+            owner.append(ti)
+    ints = [c for c, d in enumerate(tabs[1].dtypes) if d != dg.FLOAT32][:2]
+    preds[30] = ("and", [("udf", ("mod", ("add", ("col", ints[0]), ("col", ints[1])), ("const", 7)), ("gt", 2)),
+                         ("gt", ints[0], 100)])
+    dts = [esc.device_table(t) for t in tabs]
+    cps = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    want = [scan.count(tabs[o], p) for p, o in zip(preds, owner)]
+    b = esc.Batch(ctx, dts, cps, owner, rows_per_thread=rpt, max_cols=max_cols, group=12)
+    assert b.count().tolist() == want
+    need = max(p.info()["ncols"] for p in cps)
+    used = b.opts()["max_cols"]
+    assert used in (4, 6, 8) and used >= max(need, max_cols)
+    # a wider predicate (five columns of an 8-column table) raises the limit
+    wide_t = next(i for i, t in enumerate(tabs) if len(t.cols) >= 6)
+    wide = ("and", [("gt", c, 0) if tabs[wide_t].dtypes[c] != dg.FLOAT32 else ("gt", c, 0.5) for c in range(5)])
+    cps2 = cps + [esc.Pred(dts[wide_t], wide)]
+    b.update(cps2, owner + [wide_t])
+    assert b.count().tolist() == want + [scan.count(tabs[wide_t], wide)]
+    assert b.opts()["max_cols"] >= 6
