@@ -84,7 +84,7 @@ __device__ __forceinline__ void run_tile(const Program *gp, int npred, const uin
                                          uint32_t (*s_cnt)[kScanBlock / 64], int wave)
 {
     for (int i = 0; i < npred; i++) {
-        const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF>(gp[i], v, valid)));
+        const uint32_t c = wave_sum((uint32_t)__popc(run_program<K, RPT, UDF, 0, true>(gp[i], v, valid)));
         if (lane_id() == 0) s_cnt[i][wave] += c;
     }
 }

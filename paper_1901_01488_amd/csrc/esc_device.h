@@ -35,6 +35,24 @@ __device__ __forceinline__ void for_slot(int s, F &&f)
     }
 }
 
+// for_slot as one switch (the compiler makes it a tree of about log2(K)
+// branches instead of a chain of up to K).
+template <int K, typename F>
+__device__ __forceinline__ void switch_slot(int s, F &&f)
+{
+    switch (s) {
+    case 0: if constexpr (K > 0) f(std::integral_constant<int, 0>{}); break;
+    case 1: if constexpr (K > 1) f(std::integral_constant<int, 1>{}); break;
+    case 2: if constexpr (K > 2) f(std::integral_constant<int, 2>{}); break;
+    case 3: if constexpr (K > 3) f(std::integral_constant<int, 3>{}); break;
+    case 4: if constexpr (K > 4) f(std::integral_constant<int, 4>{}); break;
+    case 5: if constexpr (K > 5) f(std::integral_constant<int, 5>{}); break;
+    case 6: if constexpr (K > 6) f(std::integral_constant<int, 6>{}); break;
+    default: if constexpr (K > 7) f(std::integral_constant<int, 7>{}); break;
+    }
+    static_assert(K <= 8, "eight slots at most");
+}
+
 // Per-lane mask of a row test: bit r = test(r).
 template <int RPT, typename T>
 __device__ __forceinline__ uint32_t bits_of(T &&test)
@@ -215,13 +233,58 @@ __device__ __forceinline__ void run_udf(const Insn &I, const uint32_t (&v)[KK][R
     }
 }
 
+template <int K, int RPT, bool UDF, int NT, int KK = (K > 0 ? K : 1)>
+__device__ __forceinline__ uint32_t run_program_tree(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid,
+                                                     const SlotTabs<NT> &tabs)
+{
+    uint32_t acc = valid, cm = 0;
+    uint32_t u[UDF ? RPT : 1];
+#pragma unroll
+    for (int r = 0; r < (UDF ? RPT : 1); r++) u[r] = 0;
+    const int n = P.ninsn;
+    for (int i = 0; i < n; i++) {
+        const Insn I = P.insn[i];
+        uint32_t m = 0;
+        bool on_udf = false;
+        if constexpr (UDF) {
+            if (I.op >= U_LOAD) {
+                run_udf<K, RPT>(I, v, u);
+                continue;
+            }
+            if (I.flags & F_SRC_UDF) {
+                m = run_test<RPT, NT>(I, P.kpool, tabs, u);
+                on_udf = true;
+            }
+        }
+        if (!on_udf) {
+            if (I.op == T_RANGE_I32) {
+                const uint32_t lo = (uint32_t)I.a, span = (uint32_t)I.b;
+                switch_slot<K>(I.src, [&](auto C) { m = bits_of<RPT>([&](int r) { return v[C][r] - lo <= span; }); });
+            } else {
+                switch_slot<K>(I.src, [&](auto C) { m = run_test<RPT, NT>(I, P.kpool, tabs, v[C]); });
+            }
+        }
+        if (I.flags & F_SINGLE) {
+            acc &= m;
+        } else {
+            cm |= m;
+            if (I.flags & F_END_CLAUSE) { acc &= cm; cm = 0; }
+        }
+    }
+    return acc;
+}
+
 // Runs the program on the loaded slots: returns valid & P(row) per row slot.
 // UDF = false is the variant for programs without udf instructions (it does
-// not reserve registers for the udf accumulator).
-template <int K, int RPT, bool UDF = true, int NT = 0, int KK = (K > 0 ? K : 1)>
+// not reserve registers for the udf accumulator).  TREE = true dispatches
+// on the slot with a switch and tests for the common int range first (the
+// batched kernel, whose wave streams are dominated by the interpreter's
+// scalar branches).
+template <int K, int RPT, bool UDF = true, int NT = 0, bool TREE = false, int KK = (K > 0 ? K : 1)>
 __device__ __forceinline__ uint32_t run_program(const Program &P, const uint32_t (&v)[KK][RPT], uint32_t valid,
                                                 const SlotTabs<NT> &tabs = SlotTabs<NT>{})
 {
+    if constexpr (TREE) return run_program_tree<K, RPT, UDF, NT>(P, v, valid, tabs);
     uint32_t acc = valid, cm = 0;
     uint32_t u[UDF ? RPT : 1];
 #pragma unroll
