@@ -270,6 +270,72 @@ __device__ __forceinline__ void write_tile(uint32_t bits, int64_t base, unsigned
     }
 }
 
+// write_tile for a dense tile (every row exists, at least dense_min
+// qualifying): the ranks of all NJ chunks are taken first, then for each
+// projected column the loads of all NJ chunks are issued before any is
+// staged, so that a wave keeps NJ 16-byte loads per lane in flight instead
+// of one.  Output, order and cap handling are those of write_tile.
+template <int RPT>
+__device__ __forceinline__ void write_dense_tile(uint32_t bits, int64_t base, unsigned long long p0,
+                                                 const ProjArgs &pa, int32_t *rowids, unsigned long long cap,
+                                                 uint32_t *buf)
+{
+    constexpr int NJ = RPT / 4;
+    const int lane = lane_id();
+    uint32_t pre[NJ], tot[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const uint32_t nib = (bits >> (4 * j)) & 0xfu;
+        uint32_t pr = 0, t = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint64_t b = __ballot((nib >> e) & 1u);
+            pr = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, pr));
+            t += (uint32_t)__popcll(b);
+        }
+        pre[j] = pr;
+        tot[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+    }
+    // stages chunk j's values (val(e) for e = 0..3 of this lane) at output p
+    auto put = [&](int j, unsigned long long p, uint32_t *dst_base, auto &&val) {
+        const uint32_t nib = (bits >> (4 * j)) & 0xfu;
+        const uint32_t avail = (uint32_t)(p + tot[j] <= cap ? tot[j] : cap - p);
+        uint32_t slot[4];
+        uint32_t k = pre[j];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            slot[e] = k;
+            k += (nib >> e) & 1u;
+        }
+        stage_and_flush(buf, nib, slot, val, dst_base + p, avail);
+    };
+    if (rowids) {
+        unsigned long long p = p0;
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            if (tot[j] == 0) continue;
+            if (p >= cap) break;
+            const int64_t r0 = base + (int64_t)j * (4 * kWave) + lane * 4;
+            put(j, p, (uint32_t *)rowids, [&](int e) { return (uint32_t)(r0 + e); });
+            p += tot[j];
+        }
+    }
+    for (int q = 0; q < pa.nproj; q++) {
+        const uint32_t *src = pa.src[q] + base + lane * 4;
+        u32x4 x[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; j++) x[j] = __builtin_nontemporal_load((const u32x4 *)(src + j * (4 * kWave)));
+        unsigned long long p = p0;
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            if (tot[j] == 0) continue;
+            if (p >= cap) break;
+            put(j, p, pa.dst[q], [&](int e) { return x[j][e]; });
+            p += tot[j];
+        }
+    }
+}
+
 // Writes the qualifying rows of every wave tile at offsets[t] onwards, in row
 // order, from the lane masks of the count pass.  A projected column is read
 // with the tile's coalesced 16-byte loads when the tile has at least
@@ -291,6 +357,10 @@ __global__ __launch_bounds__(kScanBlock) void write_kernel(const uint32_t *tile_
         const int64_t base = t * TILE;
         const bool dense = base + TILE <= n && o1 - o0 >= dense_min;
         const uint32_t bits = tile_bits[t * kWave + lane_id()];
+        if (dense) {
+            write_dense_tile<RPT>(bits, base, o0, pa, rowids, cap, buf);
+            continue;
+        }
         write_tile<RPT>(bits, base, o0, pa, rowids, cap, buf,
                         [&](int q, int, int64_t r0, uint32_t nib, const uint32_t(&slot)[4], uint32_t *dst,
                             uint32_t avail) {
