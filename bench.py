@@ -236,15 +236,22 @@ def main():
     rowids = torch.empty(cap, dtype=torch.int32, device=dev)
     outs = [torch.empty(cap, dtype=dt.cols[j].dtype, device=dev) for j in proj]
     ws = ctx.workspace(dt, True)
+    ws2 = [ws, ctx.workspace(dt, True, key="step-1")]
 
     dmat = torch.zeros(len(cps), dtype=torch.int64, device=dev)
 
     def step():
-        # the count comes back to the host (the push-down decision needs it);
-        # the materialization is enqueued behind it without a wait
+        # each count comes back to the host (the push-down decision needs
+        # it) and its materialization is enqueued behind it without a wait;
+        # the next selection's count is enqueued before the host waits, so
+        # the GPU does not idle while the host decides (two workspaces in
+        # turn keep each count's tiles for its own materialization)
+        ctx.count_begin(dt, cps[0], ws2[0], 0, stream=stream)
         for i, p in enumerate(cps):
-            ctx.count(dt, p, ws=ws, stream=stream)
-            ctx.materialize_async(dt, p, proj, rowids, outs, cap, dmat[i:i + 1], ws, stream=stream)
+            if i + 1 < len(cps):
+                ctx.count_begin(dt, cps[i + 1], ws2[(i + 1) % 2], (i + 1) % 2, stream=stream)
+            ctx.count_end(i % 2)
+            ctx.materialize_async(dt, p, proj, rowids, outs, cap, dmat[i:i + 1], ws2[i % 2], stream=stream)
 
     N = t.nrows
     step_bytes = 0

@@ -222,6 +222,22 @@ int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
 int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
                     void *dev_ws, size_t ws_bytes, void *stream, uint64_t *dev_count);
 
+/* The count split in two calls, so that a caller can enqueue more work
+ * (say, the next selection's count) before waiting for this result, and
+ * the GPU does not idle while the host decides.  esc_count_begin enqueues
+ * the scan of esc_count on the stream; its last block writes the count
+ * into a pinned host word of the context, slot `slot` (0 <= slot <
+ * ESC_COUNT_SLOTS), and an event is recorded behind it.  esc_count_end
+ * waits for that event only (not for work enqueued later) and returns the
+ * count.  A slot holds one count at a time: beginning on a slot whose
+ * count was not taken gives ESC_ERR_INVALID, as does ending a slot with no
+ * count in flight.  Tiles for a following esc_materialize are left as by
+ * esc_count.  Errors as esc_count. */
+#define ESC_COUNT_SLOTS 64
+int esc_count_begin(esc_ctx *ctx, const esc_table *t, const esc_pred *p,
+                    void *dev_ws, size_t ws_bytes, void *stream, int slot);
+int esc_count_end(esc_ctx *ctx, int slot, uint64_t *out_count);
+
 /* The selection together with its pushed-down projection (Section 2) kept
  * as a temporary table (Section 2.1): dev_rowids[r] is the r-th qualifying
  * row in ascending row order, dev_proj_out[j][r] the value of column

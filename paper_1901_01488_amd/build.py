@@ -25,7 +25,8 @@ SOURCES = [
     "esc_policy.cpp",
     "esc_types.cpp",
     "esc_api.hip",
-    "esc_scan.hip",
+    "esc_count.hip",
+    "esc_materialize.hip",
     "esc_batch.hip",
     "esc_join.hip",
     "esc_mlp.hip",

@@ -234,6 +234,9 @@ int esc_ctx_destroy(esc_ctx *ctx)
 {
     if (!ctx) return ESC_OK;
     forget_tiles(ctx, nullptr);
+    (void)set_device(ctx->device);
+    for (hipEvent_t &ev : ctx->slot_event)
+        if (ev) (void)hipEventDestroy(ev);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return ESC_OK;
@@ -353,9 +356,43 @@ int esc_count_async(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *d
     return count_launch(ctx, t, p, dev_ws, ws_bytes, (hipStream_t)stream, (unsigned long long *)dev_count, false);
 }
 
+int esc_count_begin(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws, size_t ws_bytes,
+                    void *stream, int slot)
+{
+    if (slot < 0 || slot >= ESC_COUNT_SLOTS) return fail(ESC_ERR_INVALID, "slot %d outside [0, %d)", slot, ESC_COUNT_SLOTS);
+    int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
+    if (rc) return rc;
+    if (ctx->slot_pending[slot]) return fail(ESC_ERR_INVALID, "slot %d holds a count not yet taken by esc_count_end", slot);
+    if ((rc = set_device(ctx->device))) return rc;
+    hipError_t e;
+    if (!ctx->slot_event[slot] &&
+        (e = hipEventCreateWithFlags(&ctx->slot_event[slot], hipEventDisableTiming)) != hipSuccess) {
+        ctx->slot_event[slot] = nullptr;
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // the kernel's last block writes the count into the slot's pinned word
+    if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx->pinned_dev + kSlotWord + slot, false))) return rc;
+    if ((e = hipEventRecord(ctx->slot_event[slot], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->slot_pending[slot] = true;
+    return ESC_OK;
+}
+
+int esc_count_end(esc_ctx *ctx, int slot, uint64_t *out_count)
+{
+    if (!ctx || !out_count) return fail(ESC_ERR_INVALID, "null argument");
+    if (slot < 0 || slot >= ESC_COUNT_SLOTS) return fail(ESC_ERR_INVALID, "slot %d outside [0, %d)", slot, ESC_COUNT_SLOTS);
+    if (!ctx->slot_pending[slot]) return fail(ESC_ERR_INVALID, "slot %d has no count in flight", slot);
+    if (int rc = set_device(ctx->device)) return rc;
+    hipError_t e = hipEventSynchronize(ctx->slot_event[slot]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    ctx->slot_pending[slot] = false;
+    *out_count = ((volatile unsigned long long *)ctx->pinned)[kSlotWord + slot];
+    return ESC_OK;
+}
+
 }  // extern "C"
 
-__global__ void copy_u64_kernel(unsigned long long *dst, const unsigned long long *src) { *dst = *src; }
 
 // Enqueues count (unless the workspace holds this predicate's tiles), scan
 // and write on the stream; the total count lands in *dev_total (device).
@@ -422,8 +459,8 @@ static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *
         // pass 1: per-wave-tile counts and lane masks, unless the preceding
         // count left them (then the launch only checks the workspace's stamp)
         if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, &h->result, true, expect))) return rc;
-        // pass 2: offsets in row order (total in h->result)
-        launch_scan(tiles, L.ntiles, offsets, h, s);
+        // pass 2: offsets in row order (total in h->result and dev_total)
+        launch_scan(tiles, L.ntiles, offsets, h, dev_total != &h->result ? dev_total : nullptr, s);
         // pass 3: write
         if (capacity > 0) {
             WriteFn fn = write_fn(rpt);
@@ -435,7 +472,6 @@ static int materialize_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *
             hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, bits, offsets, t->nrows, pa,
                                dev_rowids, (unsigned long long)capacity, dense_min);
         }
-        if (dev_total != &h->result) hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(1), 0, s, dev_total, &h->result);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ESC_OK : hip_fail(e, "materialize kernel launch");

@@ -72,6 +72,9 @@ WriteFn write_fn(int rpt);
 typedef void (*ConjFn)(const Program *, int, const ColPtrs, int64_t, unsigned long long *);
 ConjFn conj_fn(int nslots, bool udf);
 void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s);
-void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s);
+// offsets of m tile counts in row order; the total goes to ws->result and,
+// when total is not null, to *total
+void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, unsigned long long *total,
+                 hipStream_t s);
 
 }  // namespace esc

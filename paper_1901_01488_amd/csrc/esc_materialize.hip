@@ -1,27 +1,17 @@
-// esc_scan.hip -- gfx950 kernels of the plain ESC scan: the COUNT(*)
-// selectivity sub-query (Section 2) and its materialization as a temporary
-// table in row order (Section 2, Section 2.1).
-//
-// Data layout: every column is a contiguous array of nrows 4-byte values
-// (int32, date32 or float32), 16-byte aligned.  The unit of work is a wave
-// tile of 64*RPT consecutive rows (esc_device.h): its columns are read with
-// coalesced 16-byte loads, the predicate program runs on registers with
-// wave-uniform control, and the qualifying rows come out as per-lane bit
-// masks.  Waves are independent; nothing per row is stored by a count.
-//
-// Materialization is order-preserving stream compaction in two passes and
-// no inter-block waiting:
-//   1. the count pass (the selectivity sub-query itself) also stores, per
-//      wave tile, its qualifying-row count and every lane's truth mask
-//      (1/32 of the bytes of one 4-byte column);
-//   2. one block scans the tile counts into row-order output offsets;
-//   3. the write pass reads the masks instead of the predicate's columns,
+// esc_materialize.hip -- gfx950 kernels that materialize a selection as a
+// temporary table in row order (Section 2, Section 2.1): order-preserving
+// stream compaction in passes with no inter-block waiting, after the count
+// pass of esc_count.hip stored per-tile counts and lane masks:
+//   1. one block scans the tile counts into row-order output offsets;
+//   2. the write pass reads the masks instead of the predicate's columns,
 //      ranks the qualifying rows of each 256-row chunk with ballot masks,
 //      compacts row ids and projected values in LDS and writes them as
 //      contiguous runs at offset + rank.
 // When the count pass was the caller's own preceding esc_count on the same
 // workspace, table and predicate (count, decide, then materialize),
-// materialization never reads the predicate's columns again.
+// materialization never reads the predicate's columns again.  A
+// single-pass compaction with decoupled look-back serves a materialization
+// with no count before it when asked for.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -35,109 +25,6 @@
 
 namespace esc {
 
-// ------------------------------------------------------------------ count
-
-// Grid-stride over wave tiles.  When to.counts is not null, every wave tile's
-// count and lane masks are stored there.  UDF = false for programs without
-// udf instructions.
-template <int K, int RPT, bool UDF>
-__global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
-                                                           WsHeader *ws, unsigned long long *out, const TileOut to)
-{
-    constexpr int TILE = kWave * RPT;
-    constexpr int KK = K > 0 ? K : 1;
-    constexpr int NW = kScanBlock / kWave;
-    const int64_t ntiles = (n + TILE - 1) / TILE;
-    const int64_t step = (int64_t)gridDim.x * NW;
-    const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
-    // the workspace already holds this count's tiles: nothing to do (the
-    // stamp is read from a previous launch's write, the same for every block)
-    if (to.expect != 0ull && ws->stamp == to.expect) return;
-    const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
-    uint32_t cnt = 0;   // per lane
-    for (int64_t t = first; t < ntiles; t += step) {
-        uint32_t v[KK][RPT];
-        load_vals<K, RPT>(cp, t * TILE, n, v);
-        const uint32_t bits = run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(t * TILE, n), tabs);
-        const uint32_t c = (uint32_t)__popc(bits);
-        if (to.counts) {
-            const uint32_t w = wave_sum(c);
-            if (lane_id() == 0) to.counts[t] = w;
-            to.bits[t * kWave + lane_id()] = bits;
-        }
-        cnt += c;
-    }
-    cnt = wave_sum(cnt);
-    __shared__ uint32_t s_cnt[NW];
-    const int wave = wave_id();
-    if (lane_id() == 0) s_cnt[wave] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long b = 0;
-        for (int w = 0; w < NW; w++) b += s_cnt[w];
-        // One 64-bit word carries both the running row count (low
-        // kTotalBits bits) and the number of blocks done (high bits), so
-        // each block's contribution is one atomic read-modify-write of one
-        // location.  All such RMWs are totally ordered and each reads the
-        // value left by the previous ones, so the block whose RMW returns
-        // gridDim.x - 1 blocks done has read the sum of every other block:
-        // exact without fences and without any order between two
-        // addresses.  That block publishes the total and resets the word,
-        // so the next launch on the workspace starts from zero.
-        const unsigned long long old = atomicAdd(&ws->total, (1ull << kTotalBits) | b);
-        if ((old >> kTotalBits) == gridDim.x - 1u) {
-            *out = (old & ((1ull << kTotalBits) - 1ull)) + b;
-            atomicExch(&ws->total, 0ull);
-            if (to.counts) ws->stamp = to.stamp;
-        }
-    }
-}
-
-// ------------------------------------------------------------------ conjuncts
-
-// Split selectivities: every conjunct program runs on each loaded wave tile;
-// a running AND of their masks gives the prefix conjunctions.  Per-wave sums
-// go to LDS, then one u64 atomic per counter per block.  out[i] = rows of
-// conjunct i, out[kMaxConj + i] = rows of conjuncts 0..i.
-template <int K, int RPT, bool UDF>
-__global__ __launch_bounds__(kScanBlock) void conj_kernel(const Program *__restrict__ progs, int nconj,
-                                                          const ColPtrs cp, int64_t n, unsigned long long *out)
-{
-    constexpr int TILE = kWave * RPT;
-    constexpr int KK = K > 0 ? K : 1;
-    constexpr int NW = kScanBlock / kWave;
-    __shared__ uint32_t s_acc[NW][2 * kMaxConj];
-    const int wave = wave_id();
-    for (int i = threadIdx.x; i < NW * 2 * kMaxConj; i += kScanBlock) (&s_acc[0][0])[i] = 0;
-    __syncthreads();
-    const int64_t ntiles = (n + TILE - 1) / TILE;
-    const int64_t step = (int64_t)gridDim.x * NW;
-    for (int64_t t = (int64_t)blockIdx.x * NW + wave; t < ntiles; t += step) {
-        uint32_t v[KK][RPT];
-        load_vals<K, RPT>(cp, t * TILE, n, v);
-        const uint32_t valid = valid_bits<RPT>(t * TILE, n);
-        uint32_t prefix = valid;
-        for (int i = 0; i < nconj; i++) {
-            const uint32_t m = run_program<K, RPT, UDF>(progs[i], v, valid);
-            prefix &= m;
-            const uint32_t c1 = wave_sum((uint32_t)__popc(m));
-            const uint32_t c2 = wave_sum((uint32_t)__popc(prefix));
-            if (lane_id() == 0) {
-                s_acc[wave][i] += c1;
-                s_acc[wave][kMaxConj + i] += c2;
-            }
-        }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * kMaxConj; i += kScanBlock) {
-        if ((i % kMaxConj) >= nconj) continue;
-        unsigned long long c = 0;
-#pragma unroll
-        for (int w = 0; w < NW; w++) c += s_acc[w][i];
-        if (c) atomicAdd(&out[i], c);
-    }
-}
-
 // ------------------------------------------------------------------ scan
 
 // Exclusive scan of m per-tile counts into offsets[0..m]; offsets[m] is the
@@ -146,7 +33,7 @@ __global__ __launch_bounds__(kScanBlock) void conj_kernel(const Program *__restr
 // 16-byte loads, coalesced across the block), the thread totals are scanned
 // with wave shuffles and a 16-entry LDS pass, and a carry links the rounds.
 __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *counts, int64_t m, uint32_t *offsets,
-                                                    WsHeader *ws)
+                                                    WsHeader *ws, unsigned long long *total)
 {
     constexpr int PER = 16, NT = 1024, NWV = NT / 64;
     __shared__ uint32_t s_wave[NWV];
@@ -204,6 +91,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const uint32_t *counts, int6
     if (t == 0) {
         offsets[m] = s_carry;
         ws->result = s_carry;
+        if (total) *total = s_carry;
     }
 }
 
@@ -470,66 +358,6 @@ __global__ void zero_kernel(unsigned long long *p, int64_t nwords)
 
 // ------------------------------------------------------------------ dispatch tables
 
-template <int RPT, bool UDF, int... Ks>
-constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
-{
-    CountFn t[] = {count_kernel<Ks, RPT, UDF>...};
-    return t[k];
-}
-
-// variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
-// up to four column slots, 16 above (32 rows of five or more columns no
-// longer fit the register file); variant 2: 8 rows per lane; variant 3 (the
-// default): variant 1 when the count stores its tiles for a
-// materialization, else 32 rows per lane for one or two columns, 16 for
-// more, and twice the blocks for one column.  Measured on the 60M-row star
-// table: plain counts 6.05 TB/s back to back against 5.9 for variant 1
-// (one-column counts 5.2 against 4.8), while counts that store tiles keep
-// variant 1 (with 16 rows per lane they store twice the mask bytes and the
-// offset scan has twice the tiles: 154 against 145 us per count).
-int count_rpt(int variant, int k, int ninsn, bool tiles)
-{
-    if (variant == 2) return 8;
-    if (variant == 3 && !tiles) return k <= 2 ? 32 : 16;
-    // plain counts of three or more columns: 16 rows per lane when the
-    // program is one test per column; longer programs are interpreted once
-    // per wave tile and keep 32 rows per lane to spread that over more rows
-    if (variant == 4 && !tiles) return k <= 2 || ninsn > k ? 32 : 16;
-    return variant == 0 || k > 4 ? 16 : 32;
-}
-
-// blocks of four waves per CU; one-column counts run two to keep enough
-// loads in flight (variant 3: plain counts only; variant 4: also counts
-// that store tiles)
-int count_bpc(int variant, int k, int bpc, bool tiles)
-{
-    if (k > 1 || variant < 3 || (tiles && variant == 3)) return bpc;
-    return 2 * bpc;
-}
-
-CountFn count_fn(int k, int ninsn, int variant, bool udf, bool tiles)
-{
-    using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (count_rpt(variant, k, ninsn, tiles)) {
-    case 8: return udf ? count_table_impl<8, true>(k, S{}) : count_table_impl<8, false>(k, S{});
-    case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
-    default: return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
-    }
-}
-
-template <bool UDF, int... Ks>
-constexpr ConjFn conj_table_impl(int k, std::integer_sequence<int, Ks...>)
-{
-    ConjFn t[] = {conj_kernel<Ks, 16, UDF>...};
-    return t[k];
-}
-
-ConjFn conj_fn(int nslots, bool udf)
-{
-    using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    return udf ? conj_table_impl<true>(nslots, S{}) : conj_table_impl<false>(nslots, S{});
-}
-
 template <bool UDF, int... Ks>
 constexpr CompactFn compact_table_impl(int k, std::integer_sequence<int, Ks...>)
 {
@@ -556,9 +384,10 @@ void launch_zero(unsigned long long *p, int64_t nwords, hipStream_t s)
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, nwords);
 }
 
-void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, hipStream_t s)
+void launch_scan(const uint32_t *counts, int64_t m, uint32_t *offsets, WsHeader *ws, unsigned long long *total,
+                 hipStream_t s)
 {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, m, offsets, ws);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, m, offsets, ws, total);
 }
 
 }  // namespace esc

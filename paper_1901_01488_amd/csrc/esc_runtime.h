@@ -17,7 +17,14 @@ struct esc_ctx {
     int dense_shift = 7;                    // projections of a tile read whole when >= tile rows >> shift qualify
     int cold_compact = 0;                   // a materialization without a count first: single pass (1) or count, scan, write (0)
     void *scratch = nullptr;                // this device's static scratch (esc_materialize_noalloc)
+    hipEvent_t slot_event[ESC_COUNT_SLOTS] = {};   // esc_count_begin / esc_count_end
+    bool slot_pending[ESC_COUNT_SLOTS] = {};
 };
+
+// words of the pinned block: [0, kSlotWord) read-backs of the blocking calls,
+// then one word per esc_count_begin slot
+constexpr int kSlotWord = 256;
+static_assert(kSlotWord + ESC_COUNT_SLOTS <= 512, "the slots fit the 4 KiB pinned block");
 
 namespace esc {
 

@@ -107,6 +107,8 @@ def lib():
             "esc_workspace_init": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "esc_count": ([vp, vp, vp, vp, ctypes.c_size_t, vp, P(u64)], ctypes.c_int),
             "esc_count_async": ([vp, vp, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+            "esc_count_begin": ([vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.c_int], ctypes.c_int),
+            "esc_count_end": ([vp, ctypes.c_int, P(u64)], ctypes.c_int),
             "esc_materialize": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, P(u64)],
                                 ctypes.c_int),
             "esc_materialize_async": ([vp, vp, vp, vp, ctypes.c_int, vp, vp, u64, vp, ctypes.c_size_t, vp, vp],
@@ -392,6 +394,17 @@ class Context:
     def count_async(self, table: Table, pred: Pred, dev_out, ws, stream=None):
         check(lib().esc_count_async(self.h, table.h, pred.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                     _stream_handle(stream), ctypes.c_void_p(dev_out.data_ptr())))
+
+    def count_begin(self, table: Table, pred: Pred, ws, slot, stream=None):
+        """Enqueues the count; its result waits in the context's host slot."""
+        check(lib().esc_count_begin(self.h, table.h, pred.h, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream_handle(stream), int(slot)))
+
+    def count_end(self, slot) -> int:
+        """Waits for the count begun on this slot and returns it."""
+        out = ctypes.c_uint64()
+        check(lib().esc_count_end(self.h, int(slot), ctypes.byref(out)))
+        return out.value
 
     def materialize(self, table: Table, pred: Pred, proj, rowids, outs, capacity, ws=None, stream=None,
                     allow_overflow=False):

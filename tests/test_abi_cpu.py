@@ -118,6 +118,9 @@ def test_null_arguments():
     out = ctypes.c_uint64()
     assert L.esc_count(None, None, None, None, 0, None, ctypes.byref(out)) == esc.ERR_INVALID
     assert L.esc_pred_get_info(None, None) == esc.ERR_INVALID
+    assert L.esc_count_begin(None, None, None, None, 0, None, 0) == esc.ERR_INVALID
+    assert L.esc_count_begin(None, None, None, None, 0, None, -1) == esc.ERR_INVALID
+    assert L.esc_count_end(None, 0, ctypes.byref(out)) == esc.ERR_INVALID
 
 
 def test_table_create_errors():
@@ -140,6 +143,10 @@ def test_scan_on_schema_only_table_is_rejected(schema):
     rc = esc.lib().esc_count(ctypes.c_void_p(16), schema.h, p.h, ctypes.c_void_p(256), 4096, None, ctypes.byref(out))
     assert rc == esc.ERR_INVALID
     assert "schema-only" in esc.last_error()
+    rc = esc.lib().esc_count_begin(ctypes.c_void_p(16), schema.h, p.h, ctypes.c_void_p(256), 4096, None, 3)
+    assert rc == esc.ERR_INVALID and "schema-only" in esc.last_error()
+    rc = esc.lib().esc_count_begin(ctypes.c_void_p(16), schema.h, p.h, ctypes.c_void_p(256), 4096, None, 64)
+    assert rc == esc.ERR_INVALID and "slot" in esc.last_error()
 
 
 def test_normalisation_info(schema):

@@ -339,6 +339,52 @@ def test_materialize_async_matches_sync(ctx):
                 assert bool((ids_a[k:] == -1).all())
 
 
+def test_count_begin_end_pipelined(ctx):
+    """esc_count_begin / esc_count_end: counts of several selections in
+    flight on distinct slots equal the oracle's; a materialization enqueued
+    after the next selection's count (the pipelined decide loop, two
+    workspaces in turn) reuses its own tiles and equals the blocking call's;
+    misuse of a slot is refused."""
+    import torch
+    t = dg.table_star(1_200_003, seed=95)
+    dt = esc.device_table(t)
+    specs = dg.preds_star(t, 8, seed=96)
+    cps = [esc.Pred(dt, s_) for s_ in specs]
+    want = [scan.count(t, s_) for s_ in specs]
+    ws = [ctx.workspace(dt, True, key=("pipe", k)) for k in range(2)]
+    wsc = ctx.workspace(dt, False, key="pipe-count")
+    # three counts in flight, taken out of order
+    for k in range(3):
+        ctx.count_begin(dt, cps[k], wsc if k == 2 else ws[k], slot=10 + k)
+    assert [ctx.count_end(12), ctx.count_end(10), ctx.count_end(11)] == [want[2], want[0], want[1]]
+    # the pipelined loop of the star step
+    cap = max(want)
+    ids = [torch.full((cap,), -1, dtype=torch.int32, device="cuda") for _ in specs]
+    outs = [[torch.zeros(cap, dtype=dt.cols[j].dtype, device="cuda") for j in dg.STAR_PROJECTION] for _ in specs]
+    dmat = torch.zeros(len(specs), dtype=torch.int64, device="cuda")
+    ctx.count_begin(dt, cps[0], ws[0], slot=0)
+    got = []
+    for i in range(len(specs)):
+        if i + 1 < len(specs):
+            ctx.count_begin(dt, cps[i + 1], ws[(i + 1) % 2], slot=(i + 1) % 2)
+        got.append(ctx.count_end(i % 2))
+        ctx.materialize_async(dt, cps[i], dg.STAR_PROJECTION, ids[i], outs[i], cap, dmat[i:i + 1], ws[i % 2])
+    torch.cuda.synchronize()
+    assert got == want and dmat.cpu().tolist() == want
+    for i, s_ in enumerate(specs):
+        _, wids, wouts = scan.materialize(t, s_, dg.STAR_PROJECTION)
+        assert_same_rows(ids[i][:want[i]].cpu().numpy(), [o[:want[i]].cpu().numpy() for o in outs[i]], wids, wouts)
+    # misuse: a slot whose count was not taken, a slot with nothing in flight
+    ctx.count_begin(dt, cps[0], wsc, slot=5)
+    with pytest.raises(esc.EscError):
+        ctx.count_begin(dt, cps[1], wsc, slot=5)
+    assert ctx.count_end(5) == want[0]
+    with pytest.raises(esc.EscError):
+        ctx.count_end(5)
+    with pytest.raises(esc.EscError):
+        ctx.count_begin(dt, cps[0], wsc, slot=64)
+
+
 def test_graph_capture_replay(ctx):
     """esc_count_async and esc_materialize_async enqueue kernels only (no
     memset or host copy), so they can be captured into a HIP graph; every
