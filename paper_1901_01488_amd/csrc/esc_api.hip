@@ -373,7 +373,12 @@ int esc_count_begin(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *d
     hipStream_t s = (hipStream_t)stream;
     // the kernel's last block writes the count into the slot's pinned word
     if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx->pinned_dev + kSlotWord + slot, false))) return rc;
-    if ((e = hipEventRecord(ctx->slot_event[slot], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventRecord(ctx->slot_event[slot], s)) != hipSuccess) {
+        // the scan is enqueued but nothing marks its end: let it finish, so
+        // that the slot's word is not written after this call returns
+        (void)hipStreamSynchronize(s);
+        return hip_fail(e, "hipEventRecord");
+    }
     ctx->slot_pending[slot] = true;
     return ESC_OK;
 }
