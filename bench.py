@@ -453,6 +453,35 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
     assert dout.cpu().tolist() == plain
     n = len(cps)
     tbm, tsm, tam = float(np.median(tb)), float(np.median(ts)), float(np.median(ta))
+    decided = [p.info()["constant"] != 0 for p in cps]
+    scanned_rows = sum(tabs[o].nrows for o, d in zip(owner, decided) if not d)
+    # the same predicates compiled as written (no intersection of conjuncts
+    # on one column): every one is scanned
+    log("batched workload: without conjunct simplification")
+    os.environ["ESC_SIMPLIFY"] = "0"
+    try:
+        raw = [esc.Pred(dts[o], p) for p, o in zip(preds, owner)]
+    finally:
+        del os.environ["ESC_SIMPLIFY"]
+    o_ = b.opts()
+    braw = esc.Batch(ctx, dts, raw, owner, rows_per_thread=o_["rows_per_thread"], group=o_["group"],
+                     chunk_rows=o_["chunk_rows"], max_cols=o_["max_cols"])
+    assert braw.count().tolist() == plain
+    tr = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        braw.count()
+        tr.append(time.perf_counter() - a)
+    tra = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for i, (p, o) in enumerate(zip(raw, owner)):
+            ctx.count_async(dts[o], p, dout[i:i + 1], aws)
+        torch.cuda.synchronize()
+        tra.append(time.perf_counter() - a)
+    assert dout.cpu().tolist() == plain
+    trm, tram = float(np.median(tr)), float(np.median(tra))
     bytes_batched = 0
     for ti, t in enumerate(tabs):
         used = set()
@@ -466,7 +495,13 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
             "batched_speedup_vs_best_plain": round(min(tsm, tam) / tbm, 2),
             "batched_ms": round(tbm * 1e3, 3), "batched_GBps_distinct_columns": round(bytes_batched / tbm / 1e9, 1),
             "batched_opts": b.opts(), "autotune_s": round(tune_s, 2),
-            "batched_row_predicates_per_s": round(32 * sum(t.nrows for t in tabs) / tbm, 1),
+            "batched_decided_by_the_compiler": int(sum(decided)),
+            "batched_row_predicates_per_s": round(scanned_rows / tbm, 1),
+            "without_simplification": {"batched_ms": round(trm * 1e3, 3),
+                                       "batched_predicates_per_s": round(n / trm, 1),
+                                       "plain_async_predicates_per_s": round(n / tram, 1),
+                                       "batched_speedup_vs_plain_async": round(tram / trm, 2),
+                                       "batched_row_predicates_per_s": round(32 * sum(t.nrows for t in tabs) / trm, 1)},
             # from the SQ counters of profiles/batch_kernel_256preds_8tables.txt (None once the kernel changed)
             "batched_valu_issue_fraction": (lambda kv: float(kv["valu_issue_fraction (SQ_INSTS_VALU x 4 / (1024 x "
                                                             "cycles))"]) if kv else None)(
@@ -777,12 +812,13 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p, gen="mi
         count_errors += int((pl["counts"][:, cols] != plain["counts"][:, cols]).sum())
         count_errors += int((ba["counts"][:, cols] != plain["counts"][:, cols]).sum())
         for g in (ga, gs):
-            count_errors += int((g["counts"][g["routed"]] != plain["counts"][g["routed"]]).sum())
+            ex = g["routed"] | g["known"]
+            count_errors += int((g["counts"][ex] != plain["counts"][ex]).sum())
     nrows = [t.nrows for t in tabs]
     exact_sel = plain["counts"] / np.array(nrows, np.float64)
 
     def agreement(gated, gcfg):
-        r = gated["routed"]
+        r = gated["routed"] | gated["known"]   # counted, or decided by the compiler
         est_sel = np.where(r, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
         ex, es = planning.plans(exact_sel, nrows, gcfg), planning.plans(est_sel, nrows, gcfg)
         return (float(np.mean([planning.agree(a, b, s, gcfg) for a, b, s in zip(ex, es, exact_sel)])),
@@ -792,6 +828,7 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p, gen="mi
     agree_tie, agree_tie_strict = agreement(modes[(kinds[0][0], 0)][2], tie_cfg)
     agree_strict, _ = agreement(modes[(kinds[0][0], 0)][3], planning.GateConfig(beta=1.5, tie_sel=0.0))
     empty = [float(np.mean(plain["counts"][:, t] == 0)) for t in range(3)]
+    decided = [float(np.mean(modes[(kinds[0][0], 0)][2]["known"][:, t])) for t in range(3)]
     ties = float(np.mean((exact_sel[:, 0] <= tie_cfg.tie_sel) & (exact_sel[:, 1] <= tie_cfg.tie_sel)))
     # the oracle checks exact counts of R and S (all, or a seeded sample) and
     # a seeded sample of P
@@ -809,7 +846,7 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p, gen="mi
         oracle_rows += len(idx) * tab.nrows
         oracle_s += sec
     strip = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()
-                       if k not in ("counts", "est", "routed")}
+                       if k not in ("counts", "est", "routed", "known")}
     table = {}
     for (kind, probe), (pl, ba, ga, gs) in modes.items():
         table[f"{kind}_exact_probe{probe}"] = {
@@ -830,6 +867,7 @@ def planning_leg(ctx, nq, train_n, epochs, offered, oracle_rs, oracle_p, gen="mi
         "gate": f"beta 1.5, tau 0.05, join-order ties below selectivity {tie_cfg.tie_sel:g} (no_ties: every order "
                 "counts)",
         "empty_selection_fraction": [round(v, 3) for v in empty],
+        "decided_by_the_compiler_fraction": [round(v, 3) for v in decided],
         "queries_with_tied_join_order": round(ties, 3),
         "plan_agreement_with_exact": round(agree_tie, 4),
         "plan_agreement_with_exact_ties_compared": round(agree_tie_strict, 4),

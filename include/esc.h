@@ -211,7 +211,9 @@ int esc_workspace_init(esc_ctx *ctx, void *dev_ws, size_t ws_bytes, void *stream
 
 /* Exact COUNT(*) of the selection (Section 2: the selectivity sub-query
  * with a temporary COUNT aggregate).  Blocks until the count is on the
- * host.  With a materialization-sized workspace the per-tile counts and
+ * host.  A predicate the compiler decided (always true or always false,
+ * e.g. contradictory conjuncts on one column) or an empty table is
+ * answered on the host without any GPU work.  With a materialization-sized workspace the per-tile counts and
  * truth masks are left in it for a following esc_materialize of the same
  * predicate. */
 int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p,

@@ -342,6 +342,13 @@ int esc_count(esc_ctx *ctx, const esc_table *t, const esc_pred *p, void *dev_ws,
     // 33.7 against 24.1 us per call on a 1M-row table)
     int rc = check_scan_args(ctx, t, p, dev_ws, ws_bytes, sizeof(WsHeader));
     if (rc) return rc;
+    // a predicate the compiler decided (always true or false) or an empty
+    // table: the count is known without a scan, and nothing is enqueued
+    const int pf = p->prog.flags;
+    if ((pf & (P_ALWAYS_TRUE | P_ALWAYS_FALSE)) || t->nrows == 0) {
+        *out_count = (pf & P_ALWAYS_TRUE) ? (uint64_t)t->nrows : 0u;
+        return ESC_OK;
+    }
     if ((rc = count_launch(ctx, t, p, dev_ws, ws_bytes, s, ctx->pinned_dev, false))) return rc;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <atomic>
 #include <new>
 #include <set>
@@ -171,6 +172,14 @@ int slot_rotation(const std::vector<uint32_t> &keys)
         if (ok) return r;
     }
     return -1;
+}
+
+// Whether conjuncts on one column are intersected at compile time
+// (ESC_SIMPLIFY=0 turns it off, for comparisons).
+bool simplify_enabled()
+{
+    const char *e = getenv("ESC_SIMPLIFY");
+    return !(e && atoi(e) == 0);
 }
 
 // Smallest IN-list compiled to a slot table (ESC_IN_HASH_MIN; 0 = never).
@@ -389,6 +398,179 @@ int to_cnf(Ctx &C, int &pos, int depth, Cnf &out)
     return ESC_OK;
 }
 
+// ---- conjunct simplification
+//
+// The value set a non-udf leaf accepts on its column: an int or float
+// interval, or a finite set of ints or floats (float sets hold no NaN and
+// one zero, +0).
+struct ValSet {
+    bool fl = false, set = false;
+    int64_t lo = INT32_MIN, hi = INT32_MAX;   // int interval
+    float flo = -INFINITY, fhi = INFINITY;    // float interval (compared as floats: -0 == +0)
+    std::vector<int64_t> iv;                  // int set, sorted, unique
+    std::vector<float> fv;                    // float set
+};
+
+bool value_set(const Leaf &L, ValSet &V)
+{
+    if (L.udf || L.kind != L_TEST) return false;
+    const Insn &t = L.test;
+    V = ValSet{};
+    switch (t.op) {
+    case T_RANGE_I32: V.lo = t.a; V.hi = (int64_t)t.a + (uint32_t)t.b; return true;
+    case T_BITSET: {
+        const uint64_t bits = ((uint64_t)(uint32_t)t.c << 32) | (uint32_t)t.b;
+        V.set = true;
+        for (int i = 0; i < 64; i++)
+            if ((bits >> i) & 1u) V.iv.push_back((int64_t)t.a + i);
+        return true;
+    }
+    case T_IN_I32:
+        V.set = true;
+        for (uint32_t k : L.kvals) V.iv.push_back((int32_t)k);
+        std::sort(V.iv.begin(), V.iv.end());
+        return true;
+    case T_RANGE_F32: V.fl = true; V.flo = bitsf((uint32_t)t.a); V.fhi = bitsf((uint32_t)t.b); return true;
+    case T_IN_F32:
+        V.fl = V.set = true;
+        for (uint32_t k : L.kvals) V.fv.push_back(bitsf(k));
+        return true;
+    }
+    return false;
+}
+
+bool contains(const ValSet &V, int64_t x) { return V.set ? std::binary_search(V.iv.begin(), V.iv.end(), x) : V.lo <= x && x <= V.hi; }
+bool contains(const ValSet &V, float x)
+{
+    if (!V.set) return V.flo <= x && x <= V.fhi;
+    for (float y : V.fv)
+        if (y == x) return true;
+    return false;
+}
+
+// a ∩ b (same column, same kind of values)
+ValSet intersect(const ValSet &a, const ValSet &b)
+{
+    ValSet r;
+    r.fl = a.fl;
+    if (!a.set && !b.set) {
+        r.lo = std::max(a.lo, b.lo);
+        r.hi = std::min(a.hi, b.hi);
+        r.flo = std::max(a.flo, b.flo);
+        r.fhi = std::min(a.fhi, b.fhi);
+        return r;
+    }
+    const ValSet &s = a.set ? a : b, &o = a.set ? b : a;
+    r.set = true;
+    if (r.fl) {
+        for (float x : s.fv)
+            if (contains(o, x)) r.fv.push_back(x);
+    } else {
+        for (int64_t x : s.iv)
+            if (contains(o, x)) r.iv.push_back(x);
+    }
+    return r;
+}
+
+bool empty(const ValSet &V)
+{
+    if (V.set) return V.fl ? V.fv.empty() : V.iv.empty();
+    return V.fl ? !(V.flo <= V.fhi) : V.lo > V.hi;
+}
+
+// every value a accepts is accepted by b
+bool subset(const ValSet &a, const ValSet &b)
+{
+    if (a.set) {
+        if (a.fl) {
+            for (float x : a.fv)
+                if (!contains(b, x)) return false;
+        } else {
+            for (int64_t x : a.iv)
+                if (!contains(b, x)) return false;
+        }
+        return true;
+    }
+    if (b.set) return false;   // an interval inside a finite set: not checked
+    return a.fl ? (b.flo <= a.flo && a.fhi <= b.fhi) : (b.lo <= a.lo && a.hi <= b.hi);
+}
+
+// a leaf testing V on column col (kind L_FALSE when V is empty)
+int leaf_of(const ValSet &V, int col, Leaf &L)
+{
+    L = Leaf{};
+    int rc;
+    if (V.fl) {
+        rc = V.set ? float_test(ESC_IN, V.fv, L) : float_range(V.flo, V.fhi, L);
+    } else if (V.set) {
+        if (V.iv.empty()) { L.kind = L_FALSE; return ESC_OK; }
+        rc = int_set(std::vector<int32_t>(V.iv.begin(), V.iv.end()), L);
+    } else {
+        rc = int_range(V.lo, V.hi, L);
+    }
+    L.test.src = (uint8_t)col;
+    return rc;
+}
+
+// Within the AND of the CNF, the single-leaf clauses on one column are
+// replaced by one leaf testing their intersection (empty: the predicate is
+// false); then each multi-leaf clause loses the leaves that no value
+// allowed on their column can satisfy, and is dropped when one of its
+// leaves holds for every such value.  Exact: every step keeps the set of
+// rows the conjunction accepts.
+int simplify_units(Ctx &C, Cnf &cnf)
+{
+    std::map<int, ValSet> unit;          // column -> allowed values
+    std::map<int, std::vector<int>> members;
+    for (auto &c : cnf) {
+        if (c.size() != 1) continue;
+        ValSet V;
+        if (!value_set(C.leaves[c[0]], V)) continue;
+        const int col = C.leaves[c[0]].test.src;
+        auto it = unit.find(col);
+        unit[col] = it == unit.end() ? V : intersect(it->second, V);
+        members[col].push_back(c[0]);
+    }
+    Cnf out;
+    for (auto &[col, V] : unit) {
+        if (empty(V)) { cnf.assign(1, Clause{}); return ESC_OK; }
+        if (members[col].size() == 1) { out.push_back(Clause{members[col][0]}); continue; }
+        Leaf L;
+        int rc = leaf_of(V, col, L);
+        if (rc) return rc;
+        if (L.kind == L_FALSE) { cnf.assign(1, Clause{}); return ESC_OK; }
+        if (L.kind == L_TRUE) continue;
+        C.leaves.push_back(L);
+        out.push_back(Clause{(int)C.leaves.size() - 1});
+    }
+    for (auto &c : cnf) {
+        if (c.size() == 1) {
+            ValSet V;
+            if (value_set(C.leaves[c[0]], V)) continue;   // folded above
+            out.push_back(c);
+            continue;
+        }
+        Clause kept;
+        bool holds = false;
+        for (int li : c) {
+            ValSet V;
+            if (!value_set(C.leaves[li], V)) { kept.push_back(li); continue; }
+            auto it = unit.find(C.leaves[li].test.src);
+            if (it == unit.end()) { kept.push_back(li); continue; }
+            if (empty(intersect(it->second, V))) continue;   // never true here
+            if (subset(it->second, V)) { holds = true; break; }
+            kept.push_back(li);
+        }
+        if (holds) continue;
+        if (kept.empty()) { cnf.assign(1, Clause{}); return ESC_OK; }
+        out.push_back(kept);
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    cnf.swap(out);
+    return ESC_OK;
+}
+
 }  // namespace
 
 int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const esc_const *consts,
@@ -413,6 +595,10 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     p->nhashed = 0;
     bool is_false = false;
     for (auto &c : cnf) is_false = is_false || c.empty();
+    if (!is_false && simplify_enabled()) {
+        if ((rc = simplify_units(C, cnf))) return rc;
+        for (auto &c : cnf) is_false = is_false || c.empty();
+    }
     if (is_false) { P.flags = P_ALWAYS_FALSE; return ESC_OK; }
     if (cnf.empty()) { P.flags = P_ALWAYS_TRUE; return ESC_OK; }
     if (cnf.size() > (size_t)ESC_MAX_CLAUSES)

@@ -65,6 +65,14 @@ class Workload:
         self.queries = queries
         self.arrivals = np.asarray(arrivals, np.float64)
         self.cps = [[esc.Pred(tables[t], q[t]) for t in range(3)] for q in queries]
+        # counts the compiler already decided (contradictory conjuncts: 0;
+        # always true: the table's rows), -1 where a scan is needed
+        self.known = np.full((len(queries), 3), -1, np.int64)
+        for i, row in enumerate(self.cps):
+            for t, cp in enumerate(row):
+                c = cp.info()["constant"]
+                if c != 0:
+                    self.known[i, t] = tables[t].nrows if c > 0 else 0
         self.ws = [ctx.workspace(t, False, key=("plan", i)) for i, t in enumerate(tables)]
         self.batch = None   # one batched handle, re-planned per micro-batch
 
@@ -133,18 +141,26 @@ class Workload:
             need = [(q, t) for q in range(i, j) for t in range(ntabs)]
             if gate is not None:
                 need = []
-                # the build relations' selections are estimated; no plan
-                # decision reads the probe relation's (it is counted or not
-                # according to exact_probe, as in the other modes)
+                # the build relations' selections are estimated (those whose
+                # count the compiler decided are exact already: their
+                # "estimate" is that count); no plan decision reads the
+                # probe relation's (it is counted or not according to
+                # exact_probe, as in the other modes)
                 for t in range(2):
-                    x = estimators[t].features([self.cps[q][t] for q in range(i, j)])
-                    yh = estimators[t].predict(x)
+                    kn = self.known[i:j, t]
+                    todo = [q for q in range(i, j) if kn[q - i] < 0]
+                    yh = np.log(np.maximum(kn, 1) / float(nrows[t])).astype(np.float32)
+                    if todo:
+                        x = estimators[t].features([self.cps[q][t] for q in todo])
+                        yh[np.array(todo) - i] = estimators[t].predict(x)
                     est[i:j, t] = yh
-                    routed[i:j, t] |= esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows)
+                    routed[i:j, t] |= esc.gate_pushdown(yh, nrows[t], gcfg.tau, gcfg.beta, gcfg.min_rows) & (kn < 0)
                 routed[i:j, 2] = gcfg.exact_probe
                 pair = esc.gate_join_pairs(est[i:j, 0], nrows[0], est[i:j, 1], nrows[1], gcfg.beta, gcfg.tie_sel)
-                routed[i:j, 0] |= pair
-                routed[i:j, 1] |= pair
+                routed[i:j, 0] |= pair & (self.known[i:j, 0] < 0)
+                routed[i:j, 1] |= pair & (self.known[i:j, 1] < 0)
+                kn_all = self.known[i:j]
+                counts[i:j][kn_all >= 0] = kn_all[kn_all >= 0].astype(np.uint64)
                 need = [(q, t) for q in range(i, j) for t in range(3) if routed[q, t]]
             if need:
                 preds = [self.cps[q][t] for q, t in need]
@@ -167,6 +183,7 @@ class Workload:
         rep["exact_fraction"] = exact_preds / (3.0 * n)
         rep["est"] = est
         rep["routed"] = routed
+        rep["known"] = self.known >= 0   # counts the compiler decided (exact, no scan)
         return rep
 
     def _report(self, done, counts, npreds, name):

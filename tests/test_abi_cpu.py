@@ -218,6 +218,9 @@ def test_in_slot_tables(schema, monkeypatch):
     assert info(("in", 2, [np.float32(v) for v in (0.0, 2.5, -7.0)]))["nhashed"] == 1
     # pool budget (256 constants): 64 + 4 * 3 as lists leave 180, and each
     # table takes 61 more, so two of the four short lists become tables
+    # (compiled as written: intersecting the two lists on column 0 would
+    # prove the conjunction empty)
+    monkeypatch.setenv("ESC_SIMPLIFY", "0")
     lists = [("in", c, [10 + i, 5000 + i, 900000 + i]) for i, c in enumerate((0, 1, 3, 0))]
     big = ("in", 1, [7 * i * i + 3 for i in range(64)])
     pred = ("and", lists + [big])
@@ -253,3 +256,26 @@ def test_autotune_cache_file_skips_bad_entries(tmp_path):
     assert L.esc_batch_tune_cache_load(str(f).encode(), ctypes.byref(acc), ctypes.byref(rej)) == esc.OK
     assert (acc.value, rej.value) == (4, 9)
     assert L.esc_batch_tune_cache_load(str(tmp_path / "missing").encode(), None, None) == esc.ERR_INVALID
+
+
+@pytest.mark.parametrize("spec,insns,const", [
+    (("and", [("lt", 0, 50), ("gt", 0, 10)]), 1, 0),                         # one range
+    (("and", [("lt", 0, 5), ("gt", 0, 10)]), 0, -1),                         # contradiction
+    (("and", [("in", 3, [1, 5, 9, 40]), ("lt", 3, 30)]), 1, 0),              # IN filtered by the range
+    (("and", [("in", 0, [1, 2, 3]), ("in", 0, [4, 5])]), 0, -1),             # disjoint IN-lists
+    (("and", [("gt", 0, 100), ("or", [("lt", 0, 50), ("eq", 3, 3)])]), 2, 0),  # OR leaf that cannot hold
+    (("and", [("between", 0, 10, 20), ("or", [("lt", 0, 50), ("eq", 3, 3)])]), 1, 0),  # OR that always holds
+    (("and", [("lt", 2, np.float32(0.0)), ("gt", 2, np.float32(-0.0))]), 0, -1),  # no float is < 0 and > -0
+    (("and", [("between", 2, np.float32(-0.0), np.float32(0.0)), ("eq", 2, np.float32(0.0))]), 1, 0),
+    (("and", [("eq", 1, 9000), ("between", 1, 8000, 9500), ("eq", 0, 3)]), 2, 0),
+    (("and", [("gt", 0, 5), ("or", [("lt", 0, 3), ("lt", 0, 1)])]), 0, -1),  # every OR leaf excluded
+])
+def test_conjunct_simplification(schema, spec, insns, const, monkeypatch):
+    """Conjuncts on one column are intersected at compile time (exact: the
+    GPU parity tests compare the simplified programs' counts with the
+    oracle, which evaluates the predicate as written)."""
+    info = esc.Pred(schema, spec).info()
+    assert (info["ninsns"], info["constant"]) == (insns, const), info
+    monkeypatch.setenv("ESC_SIMPLIFY", "0")
+    off = esc.Pred(schema, spec).info()
+    assert off["ninsns"] >= insns and (off["constant"] == 0 or const == off["constant"])

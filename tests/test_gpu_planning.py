@@ -59,7 +59,9 @@ def test_planning_gate_gain(ctx):
             assert r[:, 2].all() == probe and r[:, 2].any() == probe
             # the plans from the gated selectivities are as good as the exact
             # plans for most queries (the estimator decides the rest)
-            est_sel = np.where(r, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
+            exact = r | gated["known"]
+            assert np.array_equal(gated["counts"][exact], full["counts"][exact])
+            est_sel = np.where(exact, gated["counts"] / np.array(nrows, np.float64), np.exp(gated["est"]))
             ok = [planning.agree(a, b, s, g) for a, b, s in
                   zip(planning.plans(exact_sel, nrows, g), planning.plans(est_sel, nrows, g), exact_sel)]
             assert np.mean(ok) > 0.85
@@ -76,4 +78,3 @@ def test_planning_gate_gain(ctx):
     plain, batched, gated, frac, _, gated_strict, frac_strict, _ = res[False]
     assert frac <= frac_strict < 2.0 / 3.0
     assert gated > batched > plain
-    assert gated_strict > batched

@@ -572,3 +572,47 @@ def test_cold_materialize_star_all_predicates(ctx, monkeypatch):
         c, ids, outs, k = _cold_materialize(ctx, dt, p, dg.STAR_PROJECTION, max(wc, 1))
         assert c == wc, i
         assert_same_rows(ids[:c], [o[:c] for o in outs], wids, wouts)
+
+
+def test_simplified_programs_match_oracle(ctx, monkeypatch):
+    """Predicates whose conjuncts repeat columns (the compiler intersects
+    them, proves some empty and drops OR leaves that cannot hold): counts,
+    row ids and projections of the simplified programs equal the oracle's,
+    which evaluates the predicates as written, and equal the counts of the
+    programs compiled without simplification."""
+    import torch
+    t = dg.table_mixed(300_007, 6, seed=97, kinds=["perm", "uniform", "zipf", "correlated", "uniform6", "lognormal"])
+    dt = esc.device_table(t)
+    f = np.float32
+    specs = dg.preds_mixed(t, 120, seed=98, min_conj=3, max_conj=8)
+    specs += [
+        ("and", [("lt", 5, f(0.0)), ("gt", 5, f(-0.0))]),
+        ("and", [("between", 5, f(-0.0), f(1e30)), ("lt", 5, f(3000.0)), ("gt", 5, f(100.0))]),
+        ("and", [("in", 5, [f(0.0), f(2980.957), f(-1.0)]), ("gt", 5, f(-0.5))]),
+        ("and", [("gt", 1, 500), ("or", [("lt", 1, 100), ("eq", 2, 7)])]),
+        ("and", [("between", 1, 10, 20), ("or", [("lt", 1, 50), ("eq", 2, 7)])]),
+        ("and", [("in", 1, [3, 17, 250, 9000]), ("between", 1, 10, 300), ("gt", 3, 20)]),
+        ("and", [("in", 2, [1, 2, 3, 4]), ("in", 2, [3, 4, 5]), ("lt", 2, 4)]),
+        ("and", [("gt", 0, 2**31 - 2), ("lt", 0, -2**31 + 1)]),
+        ("and", [("gt", 4, 10), ("or", [("lt", 4, 5), ("lt", 4, 3)])]),
+    ]
+    simplified = [esc.Pred(dt, s_) for s_ in specs]
+    monkeypatch.setenv("ESC_SIMPLIFY", "0")
+    plain = [esc.Pred(dt, s_) for s_ in specs]
+    monkeypatch.delenv("ESC_SIMPLIFY")
+    assert sum(p.info()["constant"] == -1 for p in simplified) > sum(p.info()["constant"] == -1 for p in plain)
+    assert sum(p.info()["ninsns"] for p in simplified) < sum(p.info()["ninsns"] for p in plain)
+    ws = ctx.workspace(dt, True, key="simplify")
+    for i, (s_, ps, pp) in enumerate(zip(specs, simplified, plain)):
+        want = scan.count(t, s_)
+        assert ctx.count(dt, ps, ws=ws) == want, (i, s_)
+        assert ctx.count(dt, pp, ws=ws) == want, (i, s_)
+        if i % 4 == 0 or i >= 120:
+            cap = max(want, 1)
+            ids = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+            outs = [torch.zeros(cap, dtype=dt.cols[j].dtype, device="cuda") for j in (0, 5)]
+            assert ctx.materialize(dt, ps, (0, 5), ids, outs, cap, ws=ws) == want
+            _, wids, wouts = scan.materialize(t, s_, (0, 5))
+            assert_same_rows(ids[:want].cpu().numpy(), [o[:want].cpu().numpy() for o in outs], wids, wouts)
+    b = esc.Batch(ctx, [dt], simplified, [0] * len(simplified))
+    assert b.count().tolist() == [scan.count(t, s_) for s_ in specs]
