@@ -496,6 +496,7 @@ def batched_vs_plain(ctx, esc, dg, torch, dev, reps=20):
             "batched_ms": round(tbm * 1e3, 3), "batched_GBps_distinct_columns": round(bytes_batched / tbm / 1e9, 1),
             "batched_opts": b.opts(), "autotune_s": round(tune_s, 2),
             "batched_decided_by_the_compiler": int(sum(decided)),
+            "batched_scanned_row_predicates": int(scanned_rows),
             "batched_row_predicates_per_s": round(scanned_rows / tbm, 1),
             "without_simplification": {"batched_ms": round(trm * 1e3, 3),
                                        "batched_predicates_per_s": round(n / trm, 1),
