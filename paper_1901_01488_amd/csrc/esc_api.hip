@@ -323,8 +323,8 @@ static int count_launch(esc_ctx *ctx, const esc_table *t, const esc_pred *p, voi
                        (ctx->bpc > 0 ? count_bpc(ctx->count_variant, P.nslots, ctx->bpc, tiles) : occ);
         const int64_t blocks_needed = (L.ntiles + kScanBlock / 64 - 1) / (kScanBlock / 64);
         if (grid > blocks_needed) grid = blocks_needed;
-        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), 0, s, P, slot_ptrs(t, P, ctx->nt), t->nrows,
-                           (WsHeader *)dev_ws, dev_out, to);
+        hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(kScanBlock), to.counts ? kTileBufBytes : 0, s, P,
+                           slot_ptrs(t, P, ctx->nt), t->nrows, (WsHeader *)dev_ws, dev_out, to);
         if (to.counts) remember_tiles(ctx, dev_ws, t, p, rpt, to.stamp);
     }
     hipError_t e = hipGetLastError();

@@ -26,9 +26,22 @@ namespace esc {
 
 // ------------------------------------------------------------------ count
 
+// A wave's tile records wait in LDS (masks) and in a register (counts, one
+// tile per lane) and go out kTileBuf tiles at a time: a global store inside
+// the tile loop would make the next tile's loads wait for its
+// acknowledgement (stores and loads share one counter of outstanding
+// memory operations), and with one wave per SIMD nothing hides that wait.
+__device__ __forceinline__ void flush_tiles(const TileOut &to, const uint32_t *buf, uint32_t tcnt, int64_t t0,
+                                            int64_t step, int nbuf)
+{
+    for (int j = 0; j < nbuf; j++) to.bits[(t0 + j * step) * kWave + lane_id()] = buf[j * kWave + lane_id()];
+    if (lane_id() < nbuf) to.counts[t0 + lane_id() * step] = tcnt;
+}
+
 // Grid-stride over wave tiles.  When to.counts is not null, every wave tile's
-// count and lane masks are stored there.  UDF = false for programs without
-// udf instructions.
+// count and lane masks are stored there (the launch then gives the block
+// kTileBufBytes of dynamic LDS).  UDF = false for programs without udf
+// instructions.
 template <int K, int RPT, bool UDF>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            WsHeader *ws, unsigned long long *out, const TileOut to)
@@ -43,7 +56,13 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     // stamp is read from a previous launch's write, the same for every block)
     if (to.expect != 0ull && ws->stamp == to.expect) return;
     const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
-    uint32_t cnt = 0;   // per lane
+    extern __shared__ uint32_t s_tbuf[];   // [NW][kTileBuf][kWave] lane masks
+    const int wave = wave_id();
+    uint32_t *buf = s_tbuf + wave * (kTileBuf * kWave);
+    uint32_t tcnt = 0;   // lane j: count of the j-th buffered tile
+    int nbuf = 0;
+    int64_t t0 = first;  // the first buffered tile; the others follow at step
+    uint32_t cnt = 0;    // per lane
     for (int64_t t = first; t < ntiles; t += step) {
         uint32_t v[KK][RPT];
         load_vals<K, RPT>(cp, t * TILE, n, v);
@@ -51,14 +70,19 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
         const uint32_t c = (uint32_t)__popc(bits);
         if (to.counts) {
             const uint32_t w = wave_sum(c);
-            if (lane_id() == 0) to.counts[t] = w;
-            to.bits[t * kWave + lane_id()] = bits;
+            tcnt = lane_id() == nbuf ? w : tcnt;
+            buf[nbuf * kWave + lane_id()] = bits;   // each lane reads back only its own words
+            if (++nbuf == kTileBuf) {
+                flush_tiles(to, buf, tcnt, t0, step, nbuf);
+                nbuf = 0;
+                t0 = t + step;
+            }
         }
         cnt += c;
     }
+    if (to.counts && nbuf) flush_tiles(to, buf, tcnt, t0, step, nbuf);
     cnt = wave_sum(cnt);
     __shared__ uint32_t s_cnt[NW];
-    const int wave = wave_id();
     if (lane_id() == 0) s_cnt[wave] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {

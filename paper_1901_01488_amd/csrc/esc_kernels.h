@@ -36,6 +36,12 @@ struct ProjSlots {
 // `expect` != 0 the launch first compares the header's stamp with it: when
 // they are equal the tiles of this table and predicate are already in the
 // workspace and every block returns at once.
+// wave tiles whose records a tile-storing count holds in LDS before storing
+// them, and the dynamic LDS its launch gives a block for that
+constexpr int kTileBuf = 32;
+constexpr int kTileBufBytes = (kScanBlock / 64) * kTileBuf * 64 * 4;
+static_assert(kTileBuf <= 64, "one tile count per lane");
+
 struct TileOut {
     uint32_t *counts;
     uint32_t *bits;
