@@ -38,11 +38,11 @@ __device__ __forceinline__ void flush_tiles(const TileOut &to, const uint32_t *b
     if (lane_id() < nbuf) to.counts[t0 + lane_id() * step] = tcnt;
 }
 
-// Grid-stride over wave tiles.  When to.counts is not null, every wave tile's
-// count and lane masks are stored there (the launch then gives the block
-// kTileBufBytes of dynamic LDS).  UDF = false for programs without udf
-// instructions.
-template <int K, int RPT, bool UDF>
+// Grid-stride over wave tiles.  With TILES, every wave tile's count and lane
+// masks are stored in to.counts and to.bits (the launch then gives the block
+// kTileBufBytes of dynamic LDS); a plain count carries none of that code.
+// UDF = false for programs without udf instructions.
+template <int K, int RPT, bool UDF, bool TILES>
 __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, const ColPtrs cp, int64_t n,
                                                            WsHeader *ws, unsigned long long *out, const TileOut to)
 {
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
     const int64_t first = (int64_t)blockIdx.x * NW + wave_id();
     // the workspace already holds this count's tiles: nothing to do (the
     // stamp is read from a previous launch's write, the same for every block)
-    if (to.expect != 0ull && ws->stamp == to.expect) return;
+    if (TILES && to.expect != 0ull && ws->stamp == to.expect) return;
     const SlotTabs<kMaxTables> tabs = load_tables<kMaxTables>(P);
     extern __shared__ uint32_t s_tbuf[];   // [NW][kTileBuf][kWave] lane masks
     const int wave = wave_id();
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
         load_vals<K, RPT>(cp, t * TILE, n, v);
         const uint32_t bits = run_program<K, RPT, UDF, kMaxTables>(P, v, valid_bits<RPT>(t * TILE, n), tabs);
         const uint32_t c = (uint32_t)__popc(bits);
-        if (to.counts) {
+        if constexpr (TILES) {
             const uint32_t w = wave_sum(c);
             tcnt = lane_id() == nbuf ? w : tcnt;
             buf[nbuf * kWave + lane_id()] = bits;   // each lane reads back only its own words
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
         }
         cnt += c;
     }
-    if (to.counts && nbuf) flush_tiles(to, buf, tcnt, t0, step, nbuf);
+    if (TILES && nbuf) flush_tiles(to, buf, tcnt, t0, step, nbuf);
     cnt = wave_sum(cnt);
     __shared__ uint32_t s_cnt[NW];
     if (lane_id() == 0) s_cnt[wave] = cnt;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kScanBlock) void count_kernel(const Program P, cons
         if ((old >> kTotalBits) == gridDim.x - 1u) {
             *out = (old & ((1ull << kTotalBits) - 1ull)) + b;
             atomicExch(&ws->total, 0ull);
-            if (to.counts) ws->stamp = to.stamp;
+            if (TILES) ws->stamp = to.stamp;
         }
     }
 }
@@ -153,16 +153,17 @@ __global__ __launch_bounds__(kScanBlock) void conj_kernel(const Program *__restr
 
 // ------------------------------------------------------------------ dispatch tables
 
-template <int RPT, bool UDF, int... Ks>
+template <int RPT, bool UDF, bool TILES, int... Ks>
 constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 {
-    CountFn t[] = {count_kernel<Ks, RPT, UDF>...};
+    CountFn t[] = {count_kernel<Ks, RPT, UDF, TILES>...};
     return t[k];
 }
 
 // variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
 // up to four column slots, 16 above (32 rows of five or more columns no
-// longer fit the register file); variant 2: 8 rows per lane; variant 3 (the
+// longer fit the register file); variant 2: 8 rows per lane for plain
+// counts (variant 1 for counts that store tiles); variant 3 (the
 // default): variant 1 when the count stores its tiles for a
 // materialization, else 32 rows per lane for one or two columns, 16 for
 // more, and twice the blocks for one column.  Measured on the 60M-row star
@@ -172,7 +173,7 @@ constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
 // offset scan has twice the tiles: 154 against 145 us per count).
 int count_rpt(int variant, int k, int ninsn, bool tiles)
 {
-    if (variant == 2) return 8;
+    if (variant == 2 && !tiles) return 8;
     if (variant == 3 && !tiles) return k <= 2 ? 32 : 16;
     // plain counts of three or more columns: 16 rows per lane when the
     // program is one test per column; longer programs are interpreted once
@@ -193,10 +194,16 @@ int count_bpc(int variant, int k, int bpc, bool tiles)
 CountFn count_fn(int k, int ninsn, int variant, bool udf, bool tiles)
 {
     using S = std::make_integer_sequence<int, kMaxSlots + 1>;
-    switch (count_rpt(variant, k, ninsn, tiles)) {
-    case 8: return udf ? count_table_impl<8, true>(k, S{}) : count_table_impl<8, false>(k, S{});
-    case 16: return udf ? count_table_impl<16, true>(k, S{}) : count_table_impl<16, false>(k, S{});
-    default: return udf ? count_table_impl<32, true>(k, S{}) : count_table_impl<32, false>(k, S{});
+    // counts that store tiles run 16 or 32 rows per lane (count_rpt)
+    if (tiles) {
+        if (count_rpt(variant, k, ninsn, true) == 16)
+            return udf ? count_table_impl<16, true, true>(k, S{}) : count_table_impl<16, false, true>(k, S{});
+        return udf ? count_table_impl<32, true, true>(k, S{}) : count_table_impl<32, false, true>(k, S{});
+    }
+    switch (count_rpt(variant, k, ninsn, false)) {
+    case 8: return udf ? count_table_impl<8, true, false>(k, S{}) : count_table_impl<8, false, false>(k, S{});
+    case 16: return udf ? count_table_impl<16, true, false>(k, S{}) : count_table_impl<16, false, false>(k, S{});
+    default: return udf ? count_table_impl<32, true, false>(k, S{}) : count_table_impl<32, false, false>(k, S{});
     }
 }
 
