@@ -212,7 +212,13 @@ __device__ __forceinline__ void write_dense_tile(uint32_t bits, int64_t base, un
         const uint32_t *src = pa.src[q] + base + lane * 4;
         u32x4 x[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; j++) x[j] = __builtin_nontemporal_load((const u32x4 *)(src + j * (4 * kWave)));
+        for (int j = 0; j < NJ; j++) {
+            // a lane loads its four rows only if one of them qualifies: the
+            // memory system then fetches only the sectors that hold
+            // qualifying rows, and a skipped lane's values are never staged
+            x[j] = u32x4{0u, 0u, 0u, 0u};
+            if ((bits >> (4 * j)) & 0xfu) x[j] = __builtin_nontemporal_load((const u32x4 *)(src + j * (4 * kWave)));
+        }
         unsigned long long p = p0;
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
