@@ -138,11 +138,21 @@ int int_set(std::vector<int32_t> v, Leaf &L)
 
 // ---- slot tables for IN-lists (op T_IN_HASH)
 
-// Slot of key k under rotation r: bits [r+2, r+8) of k, taken cyclically.
-int slot_of_key(uint32_t k, int r)
+// Slot of key k under hash h: for h < 32, bits [h+2, h+8) of k taken
+// cyclically (k rotated right by h); for an odd multiplier h >= 2^31, the
+// top six bits of the 32-bit product k * h (multiplicative hashing).
+int slot_of_key(uint32_t k, uint32_t h)
 {
-    const uint32_t rot = r ? (k >> r) | (k << (32 - r)) : k;
+    if (h >= 32u) return (int)((k * h) >> 26);
+    const uint32_t rot = h ? (k >> h) | (k << (32 - h)) : k;
     return (int)((rot >> 2) & 63u);
+}
+
+// The i-th candidate multiplier: odd (a bijection on 32-bit keys) with the
+// top bit set (so that it cannot be read as a rotation).
+uint32_t slot_multiplier(int i)
+{
+    return (0x9E3779B1u * (uint32_t)(2 * i + 1)) | 0x80000001u;
 }
 
 // The bit patterns a slot table must hold: the constants, plus -0.0 beside
@@ -157,20 +167,35 @@ std::vector<uint32_t> slot_keys(const Leaf &L)
     return keys;
 }
 
+// Whether hash h puts every key in a slot of its own.
+bool separates(const std::vector<uint32_t> &keys, uint32_t h)
+{
+    uint64_t used = 0;
+    for (uint32_t k : keys) {
+        const uint64_t bit = 1ull << slot_of_key(k, h);
+        if (used & bit) return false;
+        used |= bit;
+    }
+    return true;
+}
+
 // First rotation whose slots separate the keys, or -1.
-int slot_rotation(const std::vector<uint32_t> &keys)
+int64_t slot_rotation(const std::vector<uint32_t> &keys)
 {
     if (keys.empty() || keys.size() > (size_t)kSlotTable) return -1;
-    for (int r = 0; r < 32; r++) {
-        uint64_t used = 0;
-        bool ok = true;
-        for (uint32_t k : keys) {
-            const uint64_t bit = 1ull << slot_of_key(k, r);
-            ok = ok && !(used & bit);
-            used |= bit;
-        }
-        if (ok) return r;
-    }
+    for (uint32_t r = 0; r < 32; r++)
+        if (separates(keys, r)) return r;
+    return -1;
+}
+
+// First of kSlotMultipliers multipliers whose slots separate the keys, or -1
+// (for keys that differ only in bits no 6-bit window holds together).
+constexpr int kSlotMultipliers = 64;
+int64_t slot_multiplier_for(const std::vector<uint32_t> &keys)
+{
+    if (keys.empty() || keys.size() > (size_t)kSlotTable) return -1;
+    for (int i = 0; i < kSlotMultipliers; i++)
+        if (separates(keys, slot_multiplier(i))) return slot_multiplier(i);
     return -1;
 }
 
@@ -648,7 +673,8 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
     int need = 0;
     for (int li : in_leaves) need += (int)C.leaves[li].kvals.size();
     if (need > kMaxKpool) return fail(ESC_ERR_UNSUPPORTED, "predicate has more than %d IN constants", kMaxKpool);
-    std::vector<int> rot_of(C.leaves.size(), -1), table_of(C.leaves.size(), -1);
+    std::vector<int64_t> hash_of(C.leaves.size(), -1);
+    std::vector<int> table_of(C.leaves.size(), -1);
     std::vector<int32_t> bitmap_lo(C.leaves.size(), 0);
     int ntables = 0;
     {
@@ -661,15 +687,18 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
             const int n = (int)L.kvals.size();
             if (hmin <= 0 || n < hmin || need + (kSlotTable - n) > kMaxKpool) continue;
             const std::vector<uint32_t> keys = slot_keys(L);
-            const int rot = slot_rotation(keys);
+            const bool bitmap_fits =
+                L.test.op == T_IN_I32 && (int64_t)(int32_t)L.kvals.back() - (int32_t)L.kvals.front() < 32 * kSlotTable;
+            // a rotation (two ops per row), else a bitmap, else a multiplier
+            int64_t h = slot_rotation(keys);
+            if (h < 0 && !bitmap_fits) h = slot_multiplier_for(keys);
             uint32_t *tab = P.kpool + kSlotTable * ntables;
-            if (rot >= 0) {
+            if (h >= 0) {
                 // every entry holds some key, so an entry equal to x means x is a key
-                rot_of[li] = rot;
+                hash_of[li] = h;
                 for (int e = 0; e < kSlotTable; e++) tab[e] = keys[0];
-                for (uint32_t k : keys) tab[slot_of_key(k, rot)] = k;
-            } else if (L.test.op == T_IN_I32 &&
-                       (int64_t)(int32_t)L.kvals.back() - (int32_t)L.kvals.front() < 32 * kSlotTable) {
+                for (uint32_t k : keys) tab[slot_of_key(k, (uint32_t)h)] = k;
+            } else if (bitmap_fits) {
                 // int keys within 2048 of the smallest: a bitmap, 32 bits per entry
                 bitmap_lo[li] = (int32_t)L.kvals.front();
                 for (int e = 0; e < kSlotTable; e++) tab[e] = 0u;
@@ -709,9 +738,9 @@ int compile(const esc_table *schema, const esc_node *nodes, int nnodes, const es
             Insn t = L.test;
             if (!L.udf) t.src = (uint8_t)slot_of[t.src];
             if (table_of[li] >= 0) {
-                t.op = rot_of[li] >= 0 ? T_IN_HASH : T_IN_BITMAP;
+                t.op = hash_of[li] >= 0 ? T_IN_HASH : T_IN_BITMAP;
                 t.a = kSlotTable * table_of[li];
-                t.b = rot_of[li] >= 0 ? rot_of[li] : bitmap_lo[li];
+                t.b = hash_of[li] >= 0 ? (int32_t)(uint32_t)hash_of[li] : bitmap_lo[li];
                 t.c = table_of[li];
             } else if (t.op == T_IN_I32 || t.op == T_IN_F32) {
                 if (kpool_at[li] < 0) {

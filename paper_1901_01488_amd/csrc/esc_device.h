@@ -148,6 +148,21 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
             entry = kpool[I.a + (threadIdx.x & 63u)];
         }
         const uint32_t lo = (uint32_t)I.b;
+        if constexpr (NT > 0) {
+            // kernels with the tables in registers run one wave per SIMD,
+            // where nothing hides a read's latency: every row's cross-lane
+            // read is issued before any is used, so the latencies overlap
+            // (the batched kernel's other waves hide them, and it keeps
+            // the registers this takes)
+            uint32_t w[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; r++)
+                w[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(((x[r] - lo) >> 3) & 0xfcu), (int)entry);
+            return bits_of<RPT>([&](int r) {
+                const uint32_t d = x[r] - lo;
+                return d < 2048u && ((w[r] >> (d & 31u)) & 1u);
+            });
+        }
         return bits_of<RPT>([&](int r) {
             const uint32_t d = x[r] - lo;
             const uint32_t w = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((d >> 3) & 0xfcu), (int)entry);
@@ -164,11 +179,22 @@ __device__ __forceinline__ uint32_t run_test(const Insn &I, const uint32_t *kpoo
         } else {
             entry = kpool[I.a + (threadIdx.x & 63u)];
         }
-        const uint32_t rot = (uint32_t)I.b;
-        return bits_of<RPT>([&](int r) {
-            const uint32_t addr = __builtin_rotateright32(x[r], rot) & 0xfcu;
-            return (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr, (int)entry) == x[r];
-        });
+        const uint32_t h = (uint32_t)I.b;
+        auto lookup = [&](auto &&addr) {
+            if constexpr (NT > 0) {
+                uint32_t w[RPT];   // all reads in flight before the compares, as above
+#pragma unroll
+                for (int r = 0; r < RPT; r++) w[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr(x[r]), (int)entry);
+                return bits_of<RPT>([&](int r) { return w[r] == x[r]; });
+            } else {
+                return bits_of<RPT>(
+                    [&](int r) { return (uint32_t)__builtin_amdgcn_ds_bpermute((int)addr(x[r]), (int)entry) == x[r]; });
+            }
+        };
+        // byte address of the slot: a rotation's bits 2..7, or the top six
+        // bits of the product with an odd multiplier
+        if (h < 32u) return lookup([&](uint32_t v) { return __builtin_rotateright32(v, h) & 0xfcu; });
+        return lookup([&](uint32_t v) { return ((v * h) >> 24) & 0xfcu; });
     }
     }
     return 0u;

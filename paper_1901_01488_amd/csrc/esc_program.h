@@ -27,7 +27,8 @@ enum Op : uint8_t {
     T_IN_I32 = 2,      // x == kpool[a + i] for some i < b
     T_IN_F32 = 3,      // float ==, same layout
     T_BITSET = 4,      // d = (uint32)(x - a); d < 64 && bit d of (uint64)c<<32 | (uint32)b
-    T_IN_HASH = 5,     // kpool[a + h(x)] == x bitwise, h(x) = (rotr(x, b) >> 2) & 63: a
+    T_IN_HASH = 5,     // kpool[a + h(x)] == x bitwise, h(x) = (rotr(x, b) >> 2) & 63 for
+                       // b < 32, else (x * b) >> 26 (b an odd multiplier >= 2^31): a
                        // 64-entry slot table whose keys occupy distinct slots (float
                        // lists hold both zeros and no NaN, so bit equality is float
                        // equality); table c of the program, a = 64 * c

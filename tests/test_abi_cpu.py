@@ -200,20 +200,30 @@ def test_ctx_without_gpu():
 
 def test_in_slot_tables(schema, monkeypatch):
     """IN-lists of three or more sparse keys become slot-table lookups when a
-    6-bit field separates the keys; otherwise, or when the constant pool
-    cannot hold another 64-entry table, they stay compare lists."""
+    6-bit field, a bitmap or a multiplicative hash separates the keys;
+    otherwise, or when the constant pool cannot hold another 64-entry table,
+    they stay compare lists."""
     info = lambda s: esc.Pred(schema, s).info()
     assert info(("in", 0, [5, 1000, 77777]))["nhashed"] == 1
     assert info(("in", 0, [5, 1000]))["nhashed"] == 0              # two compares are cheaper
     assert info(("in", 0, list(range(0, 640, 10))))["nhashed"] == 1  # 64 keys, one per slot
     # 0, 1 and 65536: every cyclic 6-bit field misses bit 0 or bit 16, so one
-    # pair of keys always shares a slot
-    assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 0
+    # pair of keys always shares a field value, and they span more than a
+    # bitmap; the top bits of a product with an odd multiplier separate them
+    assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 1
+    # sixteen keys made of bits 0, 8, 16 and 24: a 6-bit field sees at most
+    # one of those bits (two field values for sixteen keys)
+    spread = [(i & 1) | (i >> 1 & 1) << 8 | (i >> 2 & 1) << 16 | (i >> 3 & 1) << 24 for i in range(16)]
+    assert info(("in", 0, spread))["nhashed"] == 1
     # no field separates 0, 2, 66, 130 (they need bits 1, 6 and 7), but they
-    # span less than 2048: a bitmap
+    # span less than 2048: a bitmap; one more key 2048 away: a multiplier
     assert info(("in", 0, [0, 2, 66, 130]))["nhashed"] == 1
     assert info(("in", 0, [0, 2, 66, 130, 2047]))["nhashed"] == 1
-    assert info(("in", 0, [0, 2, 66, 130, 2048]))["nhashed"] == 0
+    assert info(("in", 0, [0, 2, 66, 130, 2048]))["nhashed"] == 1
+    # 64 keys spread over the int range: no hash of either family is a
+    # perfect one, and they span more than a bitmap
+    wide = [int(v) for v in np.random.default_rng(9).choice(2**31 - 1, 64, replace=False)]
+    assert info(("in", 0, wide))["nhashed"] == 0
     # float lists: a zero constant needs both zero patterns (two slots)
     assert info(("in", 2, [np.float32(v) for v in (0.0, 2.5, -7.0)]))["nhashed"] == 1
     # pool budget (256 constants): 64 + 4 * 3 as lists leave 180, and each

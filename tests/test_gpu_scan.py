@@ -428,13 +428,20 @@ def test_in_slot_tables(ctx, monkeypatch):
     """IN-lists compiled to slot tables count exactly what the oracle counts,
     and what the compare-list form counts, on data built to hit the table
     slots of the keys with other values (keys with one bit flipped), on
-    float lists holding zeros, NaN and infinities, and on 3..64-key lists."""
+    float lists holding zeros, NaN and infinities, on 3..64-key lists, and on
+    lists that only a multiplicative slot hash separates."""
     rng = np.random.default_rng(4242)
     n = 200_003
     keys = rng.integers(-2**31, 2**31, 64, dtype=np.int64).astype(np.int32)
     step4 = (np.arange(64, dtype=np.int64) * 4 + 1_000_000).astype(np.int32)   # one key per slot
     flips = (keys.view(np.uint32) ^ (np.uint32(1) << rng.integers(0, 32, 64).astype(np.uint32))).view(np.int32)
-    icol = np.concatenate([keys, flips, step4, step4 + 2, rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)])
+    # keys made of bits 0, 8, 16 and 24 (only a multiplicative hash separates
+    # them), and each with one bit flipped
+    spread = np.array([(i & 1) | (i >> 1 & 1) << 8 | (i >> 2 & 1) << 16 | (i >> 3 & 1) << 24 for i in range(16)],
+                      np.int32)
+    sflips = (spread.view(np.uint32)[:, None] ^ (np.uint32(1) << np.arange(32, dtype=np.uint32))).view(np.int32).ravel()
+    icol = np.concatenate([keys, flips, step4, step4 + 2, spread, sflips,
+                           rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)])
     fvals = np.array([0.0, -0.0, np.nan, -np.nan, np.inf, -np.inf, 1.0, -1.0, 2.5, 1e-45, -1e-45, 3.4e38], np.float32)
     fbits = np.concatenate([fvals.view(np.uint32), np.array([0x7fc00001, 0xffc12345], np.uint32)])
     fcol = np.concatenate([fbits.view(np.float32), rng.standard_normal(64).astype(np.float32)])
@@ -447,7 +454,8 @@ def test_in_slot_tables(ctx, monkeypatch):
     for w in (3, 4, 5, 7, 10, 12, 20, 33, 64):
         preds.append(("in", 0, [int(v) for v in rng.choice(keys, w, replace=False)]))
     preds += [("in", 0, [int(v) for v in step4]), ("in", 0, [int(v) for v in step4[::3]]),
-              ("in", 0, [0, 1, 65536]),   # no separating field: stays a compare list
+              ("in", 0, [0, 1, 65536]),   # no separating field: a multiplicative hash
+              ("in", 0, [int(v) for v in spread]), ("in", 0, [int(v) for v in spread[::2]] + [int(keys[0])]),
               ("in", 1, [np.float32(0.0), np.float32(2.5), np.float32(np.inf)]),
               ("in", 1, [np.float32(-0.0), np.float32(1e-45), np.float32(-1.0), np.float32(np.nan)]),
               ("in", 1, [np.float32(v) for v in fvals]),
