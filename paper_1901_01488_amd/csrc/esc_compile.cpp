@@ -189,11 +189,14 @@ int64_t slot_rotation(const std::vector<uint32_t> &keys)
 }
 
 // First of kSlotMultipliers multipliers whose slots separate the keys, or -1
-// (for keys that differ only in bits no 6-bit window holds together).
+// (for keys that differ only in bits no 6-bit window holds together).  The
+// product is a quarter-rate integer multiply per row, so lists of fewer than
+// kMultiplierMin keys stay compare lists.
 constexpr int kSlotMultipliers = 64;
+constexpr int kMultiplierMin = 8;
 int64_t slot_multiplier_for(const std::vector<uint32_t> &keys)
 {
-    if (keys.empty() || keys.size() > (size_t)kSlotTable) return -1;
+    if (keys.size() < (size_t)kMultiplierMin || keys.size() > (size_t)kSlotTable) return -1;
     for (int i = 0; i < kSlotMultipliers; i++)
         if (separates(keys, slot_multiplier(i))) return slot_multiplier(i);
     return -1;

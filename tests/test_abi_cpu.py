@@ -209,17 +209,21 @@ def test_in_slot_tables(schema, monkeypatch):
     assert info(("in", 0, list(range(0, 640, 10))))["nhashed"] == 1  # 64 keys, one per slot
     # 0, 1 and 65536: every cyclic 6-bit field misses bit 0 or bit 16, so one
     # pair of keys always shares a field value, and they span more than a
-    # bitmap; the top bits of a product with an odd multiplier separate them
-    assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 1
+    # bitmap; a multiplicative hash would separate them, but three compares
+    # cost less than a multiply per row
+    assert info(("in", 0, [0, 1, 65536]))["nhashed"] == 0
     # sixteen keys made of bits 0, 8, 16 and 24: a 6-bit field sees at most
-    # one of those bits (two field values for sixteen keys)
+    # one of those bits (two field values for sixteen keys); the top bits of
+    # a product with an odd multiplier separate them (from eight keys on)
     spread = [(i & 1) | (i >> 1 & 1) << 8 | (i >> 2 & 1) << 16 | (i >> 3 & 1) << 24 for i in range(16)]
     assert info(("in", 0, spread))["nhashed"] == 1
+    assert info(("in", 0, spread[:8]))["nhashed"] == 1
+    assert info(("in", 0, spread[:7]))["nhashed"] == 0
     # no field separates 0, 2, 66, 130 (they need bits 1, 6 and 7), but they
-    # span less than 2048: a bitmap; one more key 2048 away: a multiplier
+    # span less than 2048: a bitmap; one more key 2048 away: a compare list
     assert info(("in", 0, [0, 2, 66, 130]))["nhashed"] == 1
     assert info(("in", 0, [0, 2, 66, 130, 2047]))["nhashed"] == 1
-    assert info(("in", 0, [0, 2, 66, 130, 2048]))["nhashed"] == 1
+    assert info(("in", 0, [0, 2, 66, 130, 2048]))["nhashed"] == 0
     # 64 keys spread over the int range: no hash of either family is a
     # perfect one, and they span more than a bitmap
     wide = [int(v) for v in np.random.default_rng(9).choice(2**31 - 1, 64, replace=False)]

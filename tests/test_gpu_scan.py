@@ -454,7 +454,7 @@ def test_in_slot_tables(ctx, monkeypatch):
     for w in (3, 4, 5, 7, 10, 12, 20, 33, 64):
         preds.append(("in", 0, [int(v) for v in rng.choice(keys, w, replace=False)]))
     preds += [("in", 0, [int(v) for v in step4]), ("in", 0, [int(v) for v in step4[::3]]),
-              ("in", 0, [0, 1, 65536]),   # no separating field: a multiplicative hash
+              ("in", 0, [0, 1, 65536]),   # no separating field, three keys: a compare list
               ("in", 0, [int(v) for v in spread]), ("in", 0, [int(v) for v in spread[::2]] + [int(keys[0])]),
               ("in", 1, [np.float32(0.0), np.float32(2.5), np.float32(np.inf)]),
               ("in", 1, [np.float32(-0.0), np.float32(1e-45), np.float32(-1.0), np.float32(np.nan)]),
