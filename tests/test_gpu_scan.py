@@ -174,6 +174,26 @@ def test_star_full_size_counts_and_rows(ctx):
         assert_same_rows(ids[:n].cpu().numpy(), [o[:n].cpu().numpy() for o in outs], wids, wouts)
 
 
+def test_offset_scan_over_several_rounds(ctx):
+    """The offset scan runs in rounds of 16384 wave tiles with a carry
+    between them: a one-column table of 2^26 + 12345 rows has 32775 tiles of
+    2048 rows, so its materialization takes three rounds (the last one
+    ragged, as is the last tile); row ids and values equal the oracle's, for
+    a dense and a sparse selection."""
+    rng = np.random.default_rng(515)
+    n = (1 << 26) + 12_345
+    col = rng.integers(0, 1000, n, dtype=np.int32)
+    t = dg.Table("rounds", n, [dg.INT32], [col], ["u"], [None])
+    dt = esc.device_table(t)
+    for pred in (("lt", 0, 500), ("eq", 0, 7)):
+        want = scan.count(t, pred)
+        got, c, ids, outs = gpu_materialize(ctx, dt, pred, [0])
+        assert got == c == want, pred
+        wc, wids, wouts = scan.materialize(t, pred, [0])
+        assert wc == want
+        assert_same_rows(ids, outs, wids, wouts)
+
+
 def test_constant_predicates_materialize(ctx):
     """Always-true and always-false predicates (folded at compile time) still
     materialize every / no row, also on a fresh workspace."""
