@@ -179,7 +179,11 @@ int count_rpt(int variant, int k, int ninsn, bool tiles)
     // program is one test per column; longer programs are interpreted once
     // per wave tile and keep 32 rows per lane to spread that over more rows
     if (variant == 4 && !tiles) return k <= 2 || ninsn > k ? 32 : 16;
-    return variant == 0 || k > 4 ? 16 : 32;
+    // counts that store tiles (variant 4): 32 rows per lane up to six
+    // columns (at one wave per SIMD their values fit in registers: 280 and
+    // 316 VGPRs for five and six), so the offset scan and the write pass
+    // handle half the tiles
+    return variant == 0 || k > (tiles && variant == 4 ? 6 : 4) ? 16 : 32;
 }
 
 // blocks of four waves per CU; one-column counts run two to keep enough
