@@ -63,6 +63,32 @@ def test_random_trees_small_tables(ctx, n):
         assert_same_rows(ids, outs, wids, wouts)
 
 
+@pytest.mark.parametrize("k", [5, 6, 7, 8])
+def test_wide_programs_materialize(ctx, k):
+    """Conjunctions over five to eight distinct columns, with and without a
+    udf leaf: the counts that store tiles for the materialization run 32 rows
+    per lane up to six columns and 16 above; counts, row ids and projected
+    values equal the oracle's (150,001 rows: many tiles and a ragged one)."""
+    rng = np.random.default_rng(900 + k)
+    n = 150_001
+    cols = [rng.integers(0, 100, n).astype(np.int32) for _ in range(8)]
+    t = dg.Table("wide", n, [dg.INT32] * 8, cols, ["u"] * 8, [None] * 8)
+    dt = esc.device_table(t)
+    for trial in range(4):
+        cs = [int(c) for c in rng.choice(8, k, replace=False)]
+        leaves = [("lt", c, int(rng.integers(55, 100))) for c in cs]
+        if trial % 2:
+            leaves[0] = ("udf", ("add", ("col", cs[0]), ("col", cs[1])), ("lt", int(rng.integers(90, 170))))
+        p = ("and", leaves)
+        want = scan.count(t, p)
+        assert want > 0
+        proj = [cs[0], cs[-1]]
+        n_gpu, c, ids, outs = gpu_materialize(ctx, dt, p, proj)
+        assert n_gpu == c == want, scan.to_sexpr(p, t.dtypes)
+        wc, wids, wouts = scan.materialize(t, p, proj)
+        assert_same_rows(ids, outs, wids, wouts)
+
+
 def test_edge_values(ctx):
     from test_oracle_scan import EDGE_CASES, edge_pred
     t = dg.table_edge_floats()
