@@ -160,17 +160,19 @@ constexpr CountFn count_table_impl(int k, std::integer_sequence<int, Ks...>)
     return t[k];
 }
 
-// variant 0: 16 rows per lane; variant 1: 32 rows per lane for programs of
-// up to four column slots, 16 above (32 rows of five or more columns no
-// longer fit the register file); variant 2: 8 rows per lane for plain
-// counts (variant 1 for counts that store tiles); variant 3 (the
-// default): variant 1 when the count stores its tiles for a
-// materialization, else 32 rows per lane for one or two columns, 16 for
-// more, and twice the blocks for one column.  Measured on the 60M-row star
-// table: plain counts 6.05 TB/s back to back against 5.9 for variant 1
-// (one-column counts 5.2 against 4.8), while counts that store tiles keep
-// variant 1 (with 16 rows per lane they store twice the mask bytes and the
-// offset scan has twice the tiles: 154 against 145 us per count).
+// Rows per lane of a count (ESC_COUNT_VARIANT selects a variant, for
+// comparisons).  variant 0: 16; variant 1: 32 for programs of up to four
+// column slots, 16 above; variant 2: 8 for plain counts (variant 1 for
+// counts that store tiles); variant 3: variant 1 when the count stores its
+// tiles for a materialization, else 32 for one or two columns and 16 for
+// more, with twice the blocks for one column; variant 4 (the default):
+// plain counts as variant 3 except that programs longer than one test per
+// column keep 32, and counts that store tiles run 32 up to six columns.
+// Measured on the 60M-row star table: plain counts 6.05 TB/s back to back
+// with variant 3 against 5.9 for variant 1 (one-column counts 5.2 against
+// 4.8); counts that store tiles with 16 rows per lane store twice the mask
+// bytes and give the offset scan twice the tiles (154 against 145 us per
+// count).
 int count_rpt(int variant, int k, int ninsn, bool tiles)
 {
     if (variant == 2 && !tiles) return 8;
